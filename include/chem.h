@@ -1,0 +1,159 @@
+/*
+ * chem.h — C ABI of the MI355X batched stiff-chemistry integrator.
+ *
+ * Every CFD cell carries the thermochemical state Phi = (T, Y_1..Y_K) at a
+ * fixed pressure p, and the library integrates dPhi/dt = f(Phi) (paper,
+ * section 2.1, Eq. 1; all K mass fractions are carried, N = K + 1) over one
+ * CFD time step dt with an adaptive Rosenbrock method.  Each step uses the
+ * analytical Jacobian and a dense LU factorisation and solve of
+ * (I/(gamma h) - J) (section 2.3, Eq. 2 is its one-stage special case).
+ *
+ * Conventions for every entry point:
+ *  - Returns 0 on success or a negative CHEM_E* code; chem_last_error() then
+ *    describes the failure (thread-local, valid until the next call).
+ *  - Per-cell failures never fail a call: they go to status[c].
+ *  - Device pointers are HIP device memory owned by the caller; "stream" is a
+ *    hipStream_t (NULL = default stream) and every call is asynchronous on it.
+ *  - State arrays are SoA: element (i, c) of an [N][ld] array is at
+ *    i * ld + c, row 0 = T in K, rows 1..K = mass fractions; ld >= ncells.
+ *  - Units: p in Pa, T in K, dt and h in s, Arrhenius constants in mol-cm-s
+ *    with theta = Ea/R in K.
+ *  - A chem_mech is used by one stream at a time.
+ */
+#ifndef CHEM_H
+#define CHEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHEM_OK 0
+#define CHEM_EINVAL (-1)       /* invalid argument (pointer, size, mechanism data) */
+#define CHEM_EHIP (-2)         /* a HIP runtime call failed */
+#define CHEM_ENOMEM (-3)       /* device allocation failed */
+#define CHEM_EUNSUPPORTED (-4) /* e.g. N or an efficiency list beyond the compiled limits */
+
+/* per-cell status codes */
+#define CHEM_CELL_OK 0
+#define CHEM_CELL_TOO_MANY_STEPS 1 /* max_steps attempts did not reach dt */
+#define CHEM_CELL_STEP_UNDERFLOW 2 /* the step size fell below h_min */
+#define CHEM_CELL_SINGULAR 3       /* I/(gamma h) - J stayed singular after 5 halvings of h */
+#define CHEM_CELL_NONFINITE 4      /* non-finite state, T <= 0, or non-finite f / J */
+#define CHEM_CELL_TAPE_FULL 5      /* adjoint only: more accepted steps than the tape holds */
+
+/* Mechanism in Chemkin form (host arrays, read during chem_load_mechanism only).
+ * Rates follow the standard Chemkin definitions that section 2.3 delegates to
+ * pyJac: k = exp(lnA) T^b exp(-theta/T); reverse rates from K_c computed with
+ * NASA-7 thermo at p_ref = 1 atm; third-body [M] = sum_k eff_rk C_k; Troe
+ * falloff k = k_inf Pr/(1+Pr) F with Pr = k0 [M] / k_inf. */
+typedef struct chem_mech_desc {
+  int32_t n_species;   /* K >= 1 */
+  int32_t n_reactions; /* R >= 0 */
+  const double* W;     /* [K] molar masses, g/mol */
+  const double* nasa7; /* [K][15]: Tmid, low-range a1..a7, high-range a1..a7 */
+  const int32_t* rtype;/* [R] 0 elementary, 1 third-body, 2 Troe falloff */
+  const int32_t* reac; /* [R][3] reactant species per molecule slot, -1 = empty */
+  const int32_t* prod; /* [R][3] product species per molecule slot, -1 = empty */
+  const double* lnA;   /* [R] */
+  const double* b;     /* [R] */
+  const double* theta; /* [R] Ea/R in K */
+  const double* eff;   /* [R][K] third-body efficiencies (ignored for type 0) */
+  const double* troe;  /* [R][4] alpha, T***, T*, T** (type 2 only) */
+  const double* low;   /* [R][3] lnA0, b0, theta0 of k0 (type 2 only) */
+} chem_mech_desc;
+
+typedef struct chem_mech chem_mech; /* opaque, library-owned */
+
+/* Integrator options; pass NULL for the defaults in brackets. */
+typedef struct chem_options {
+  int32_t method;     /* 0 ROS4 [0], 1 Rodas3 */
+  int32_t max_steps;  /* step attempts per cell [100000] */
+  double fac_safe;    /* step-size safety factor [0.9] */
+  double fac_min;     /* smallest step-size ratio [0.2] */
+  double fac_max;     /* largest step-size ratio [6] */
+  double h_min;       /* step underflow limit in s [1e-20] */
+  int32_t persistent; /* -1 auto [-1], 0 one launch slot per cell, 1 persistent grid + work queue */
+  int32_t waves_per_block; /* cells per workgroup, 0 = auto [0] */
+  int32_t grid_mult;  /* persistent grid = CUs x grid_mult workgroups, 0 = auto [0] */
+  int32_t cost_order; /* 1: the queue hands out cells by descending previous step count [0] */
+  int32_t use_graph;  /* 1: launch the reset + integrate sequence as a cached hipGraph [0] */
+} chem_options;
+
+/* Validates (element balance is not required; indices, cp > 0 on
+ * [200, 6000] K, positive W) and uploads the mechanism; *out receives a handle
+ * to release with chem_free_mechanism.  EUNSUPPORTED if K > 254 or a reaction
+ * has more than 8 non-unit efficiencies. */
+int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out);
+void chem_free_mechanism(chem_mech* mech);
+
+/* Largest N the compiled kernels accept, and the mechanism's sizes. */
+int chem_max_n(void);
+int chem_mech_sizes(const chem_mech* mech, int32_t* K, int32_t* R);
+
+/* Replace lnA, b, theta (device arrays of length R in the order of the
+ * descriptor); stream-ordered.  Used to differentiate with respect to them. */
+int chem_set_arrhenius(chem_mech* mech, const double* lnA, const double* b, const double* theta,
+                       void* stream);
+
+/* Integrate every cell over [0, dt] in place (section 2.1, Eq. 1, with the
+ * adaptive Rosenbrock step of section 2.3).
+ *  state  : device [N][ld] in/out.
+ *  h      : device [ncells] in/out step size; a value <= 0 or non-finite means
+ *           start with dt; on return the controller's last unclipped proposal,
+ *           capped at dt (the sub-step that persists between CFD steps).
+ *  steps, rejects, status : device [ncells] int32 outputs, each may be NULL.
+ *  rtol, atol : error control, err = rms(e_i / (atol + rtol max|y_i|)).
+ * Uses the library's cached hipGraph when opt->use_graph is 1. */
+int chem_integrate(const chem_mech* mech, int64_t ncells, int64_t ld, double* state, double* h, double p,
+                   double dt, double rtol, double atol, const chem_options* opt, int32_t* steps,
+                   int32_t* rejects, int32_t* status, void* stream);
+
+/* Discrete adjoint of chem_integrate (not in the paper): integrates forward
+ * recording the accepted step sizes and a checkpoint every checkpoint_every
+ * accepted steps, then sweeps the Rosenbrock steps backwards with those step
+ * sizes frozen.
+ *  state0       : device [N][ld] initial states (read only).
+ *  lambda_final : device [N][ld] dPsi/dPhi(dt) per cell.
+ *  state_final  : device [N][ld] output, may equal neither input.
+ *  lambda0      : device [N][ld] output dPsi/dPhi(0), may be NULL.
+ *  grad         : device [3][R] output (d/dlnA, d/db, d/dtheta) summed over
+ *                 cells in a fixed order (bitwise reproducible).
+ *  status       : device [ncells] int32, may be NULL (CHEM_CELL_TAPE_FULL if a
+ *                 cell needs more than max_tape accepted steps).
+ *  max_tape     : accepted steps recorded per cell (0 = 4096). */
+int chem_integrate_adjoint(const chem_mech* mech, int64_t ncells, int64_t ld, const double* state0, double* h,
+                           double p, double dt, double rtol, double atol, const chem_options* opt,
+                           const double* lambda_final, double* state_final, double* lambda0, double* grad,
+                           int32_t checkpoint_every, int32_t max_tape, int32_t* steps, int32_t* status,
+                           void* stream);
+
+/* Parity entry points for the individual steps of the method.
+ * chem_rhs      : f(Phi) of every cell, f is device [N][ld] (Eq. 1).
+ * chem_jacobian : J = df/dPhi of every cell, J is device [ncells][N][N]
+ *                 row-major (section 2.3, analytical Jacobian); f may be NULL.
+ * chem_lu_solve : for each of nmat matrices A (device [nmat][n][n] row-major,
+ *                 not modified) solves A x = b in place (b device [nmat][n]),
+ *                 LU with partial pivoting as LAPACK getrf/getrs (section 2.3);
+ *                 info[m] = 0 or the 1-based step of a zero pivot. */
+int chem_rhs(const chem_mech* mech, int64_t ncells, int64_t ld, const double* state, double p, double* f,
+             void* stream);
+int chem_jacobian(const chem_mech* mech, int64_t ncells, int64_t ld, const double* state, double p, double* J,
+                  double* f, void* stream);
+int chem_lu_solve(int64_t nmat, int32_t n, const double* A, double* b, int32_t* info, void* stream);
+
+/* Times the launch variants on the given input (on a scratch copy; the
+ * caller's arrays are not modified) and stores the fastest as the default of
+ * this mechanism.  out_variant (host int32[3], may be NULL) receives
+ * {persistent, waves_per_block, grid_mult}; out_ms (host, may be NULL) its time. */
+int chem_autotune(chem_mech* mech, int64_t ncells, int64_t ld, const double* state, const double* h, double p,
+                  double dt, double rtol, double atol, int32_t* out_variant, double* out_ms, void* stream);
+
+/* Thread-local description of the last failure. */
+const char* chem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEM_H */

@@ -594,7 +594,7 @@ CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol,
     bool accepted = false;
     while (!accepted) {
       if (attempts >= o.max_steps) { res.status = ST_TOO_MANY_STEPS; break; }
-      if (h_prop < o.h_min) { res.status = ST_UNDERFLOW; break; }
+      if (!(h_prop >= o.h_min)) { res.status = ST_UNDERFLOW; break; }
       double h = h_prop;
       bool clipped = false;
       if (h >= dt - tcur) { h = dt - tcur; clipped = true; }

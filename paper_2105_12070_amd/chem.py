@@ -1,0 +1,219 @@
+"""Python binding of the C ABI in include/chem.h (argument marshalling only).
+
+Every step of the integration runs in the HIP library ``libchem.so``; PyTorch
+only provides device memory (tensors are passed by ``data_ptr()``) and the
+current HIP stream.  Importing this module without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchem.so")
+
+CHEM_OK = 0
+ERRORS = {-1: "EINVAL", -2: "EHIP", -3: "ENOMEM", -4: "EUNSUPPORTED"}
+CELL_STATUS = {0: "OK", 1: "TOO_MANY_STEPS", 2: "STEP_UNDERFLOW", 3: "SINGULAR", 4: "NONFINITE", 5: "TAPE_FULL"}
+
+
+class ChemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Desc(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32), ("W", C.c_void_p),
+                ("nasa7", C.c_void_p), ("rtype", C.c_void_p), ("reac", C.c_void_p), ("prod", C.c_void_p),
+                ("lnA", C.c_void_p), ("b", C.c_void_p), ("theta", C.c_void_p), ("eff", C.c_void_p),
+                ("troe", C.c_void_p), ("low", C.c_void_p)]
+
+
+class Options(C.Structure):
+    """chem_options; see include/chem.h for the meaning and defaults."""
+    _fields_ = [("method", C.c_int32), ("max_steps", C.c_int32), ("fac_safe", C.c_double),
+                ("fac_min", C.c_double), ("fac_max", C.c_double), ("h_min", C.c_double),
+                ("persistent", C.c_int32), ("waves_per_block", C.c_int32), ("grid_mult", C.c_int32),
+                ("cost_order", C.c_int32), ("use_graph", C.c_int32)]
+
+    def __init__(self, method=0, max_steps=100000, fac_safe=0.9, fac_min=0.2, fac_max=6.0, h_min=1e-20,
+                 persistent=-1, waves_per_block=0, grid_mult=0, cost_order=0, use_graph=0):
+        super().__init__(method, max_steps, fac_safe, fac_min, fac_max, h_min, persistent, waves_per_block,
+                         grid_mult, cost_order, use_graph)
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2105_12070_amd.build.build() "
+                              "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        L.chem_last_error.restype = C.c_char_p
+        vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        L.chem_load_mechanism.argtypes = [C.POINTER(_Desc), C.POINTER(vp)]
+        L.chem_free_mechanism.argtypes = [vp]
+        L.chem_free_mechanism.restype = None
+        L.chem_mech_sizes.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+        L.chem_set_arrhenius.argtypes = [vp, vp, vp, vp, vp]
+        L.chem_integrate.argtypes = [vp, i64, i64, vp, vp, d, d, d, d, C.POINTER(Options), vp, vp, vp, vp]
+        L.chem_integrate_adjoint.argtypes = [vp, i64, i64, vp, vp, d, d, d, d, C.POINTER(Options), vp, vp, vp,
+                                             vp, i32, i32, vp, vp, vp]
+        L.chem_rhs.argtypes = [vp, i64, i64, vp, d, vp, vp]
+        L.chem_jacobian.argtypes = [vp, i64, i64, vp, d, vp, vp, vp]
+        L.chem_lu_solve.argtypes = [i64, i32, vp, vp, vp, vp]
+        L.chem_autotune.argtypes = [vp, i64, i64, vp, vp, d, d, d, d, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != CHEM_OK:
+        raise ChemError(rc, lib().chem_last_error().decode())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t, dtype, name):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    return t
+
+
+class Mechanism:
+    """A mechanism uploaded to the current device (owns a chem_mech handle)."""
+
+    def __init__(self, mech: dict):
+        f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        i32 = lambda a: np.ascontiguousarray(a, dtype=np.int32)
+        self._arrays = dict(W=f64(mech["W"]), nasa7=f64(mech["nasa7"]), rtype=i32(mech["rtype"]),
+                            reac=i32(mech["reac"]), prod=i32(mech["prod"]), lnA=f64(mech["lnA"]),
+                            b=f64(mech["b"]), theta=f64(mech["theta"]), eff=f64(mech["eff"]),
+                            troe=f64(mech["troe"]), low=f64(mech["low"]))
+        a = self._arrays
+        desc = _Desc(int(mech["n_species"]), int(mech["n_reactions"]),
+                     *(a[k].ctypes.data for k in ("W", "nasa7", "rtype", "reac", "prod", "lnA", "b", "theta",
+                                                  "eff", "troe", "low")))
+        h = C.c_void_p()
+        _check(lib().chem_load_mechanism(C.byref(desc), C.byref(h)))
+        self._h = h
+        self.K = int(mech["n_species"])
+        self.R = int(mech["n_reactions"])
+        self.N = self.K + 1
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_arrhenius(self, lnA, b, theta):
+        for t, n in ((lnA, "lnA"), (b, "b"), (theta, "theta")):
+            _dev(t, torch.float64, n)
+        _check(lib().chem_set_arrhenius(self._h, _ptr(lnA), _ptr(b), _ptr(theta), _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.chem_free_mechanism(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def integrate(mech: Mechanism, state, h, p, dt, rtol=1e-6, atol=1e-10, options: Options | None = None,
+              steps=None, rejects=None, status=None, ncells=None):
+    """chem_integrate on an [N, ld] float64 CUDA tensor, in place."""
+    _dev(state, torch.float64, "state")
+    _dev(h, torch.float64, "h")
+    for t, n in ((steps, "steps"), (rejects, "rejects"), (status, "status")):
+        _dev(t, torch.int32, n)
+    N, ld = state.shape
+    if N != mech.N:
+        raise ValueError(f"state has {N} rows, mechanism needs {mech.N}")
+    nc = ld if ncells is None else int(ncells)
+    opt = C.byref(options) if options is not None else None
+    _check(lib().chem_integrate(mech.handle, nc, ld, _ptr(state), _ptr(h), float(p), float(dt), float(rtol),
+                                float(atol), opt, _ptr(steps), _ptr(rejects), _ptr(status), _stream()))
+
+
+def integrate_adjoint(mech: Mechanism, state0, h, p, dt, rtol, atol, lambda_final, options: Options | None = None,
+                      checkpoint_every=8, max_tape=0, want_lambda0=True):
+    """chem_integrate_adjoint; returns (state_final, lambda0, grad[3, R], steps, status)."""
+    _dev(state0, torch.float64, "state0")
+    _dev(h, torch.float64, "h")
+    _dev(lambda_final, torch.float64, "lambda_final")
+    N, ld = state0.shape
+    out = torch.empty_like(state0)
+    lam0 = torch.empty_like(state0) if want_lambda0 else None
+    grad = torch.empty((3, mech.R), dtype=torch.float64, device=state0.device)
+    steps = torch.empty(ld, dtype=torch.int32, device=state0.device)
+    status = torch.empty(ld, dtype=torch.int32, device=state0.device)
+    opt = C.byref(options) if options is not None else None
+    _check(lib().chem_integrate_adjoint(mech.handle, ld, ld, _ptr(state0), _ptr(h), float(p), float(dt),
+                                        float(rtol), float(atol), opt, _ptr(lambda_final), _ptr(out), _ptr(lam0),
+                                        _ptr(grad), int(checkpoint_every), int(max_tape), _ptr(steps),
+                                        _ptr(status), _stream()))
+    return out, lam0, grad, steps, status
+
+
+def rhs(mech: Mechanism, state, p):
+    _dev(state, torch.float64, "state")
+    N, ld = state.shape
+    f = torch.empty_like(state)
+    _check(lib().chem_rhs(mech.handle, ld, ld, _ptr(state), float(p), _ptr(f), _stream()))
+    return f
+
+
+def jacobian(mech: Mechanism, state, p):
+    _dev(state, torch.float64, "state")
+    N, ld = state.shape
+    J = torch.empty((ld, N, N), dtype=torch.float64, device=state.device)
+    f = torch.empty_like(state)
+    _check(lib().chem_jacobian(mech.handle, ld, ld, _ptr(state), float(p), _ptr(J), _ptr(f), _stream()))
+    return J, f
+
+
+def lu_solve(A, b):
+    """Batched A x = b (A [nmat, n, n], b [nmat, n]); returns (x, info)."""
+    _dev(A, torch.float64, "A")
+    _dev(b, torch.float64, "b")
+    nmat, n, _ = A.shape
+    x = b.clone()
+    info = torch.empty(nmat, dtype=torch.int32, device=A.device)
+    _check(lib().chem_lu_solve(nmat, n, _ptr(A), _ptr(x), _ptr(info), _stream()))
+    return x, info
+
+
+def autotune(mech: Mechanism, state, h, p, dt, rtol=1e-6, atol=1e-10):
+    """Times the launch variants on (a scratch copy of) the input; returns (variant, ms)."""
+    _dev(state, torch.float64, "state")
+    _dev(h, torch.float64, "h")
+    N, ld = state.shape
+    v = (C.c_int32 * 3)()
+    ms = C.c_double()
+    _check(lib().chem_autotune(mech.handle, ld, ld, _ptr(state), _ptr(h), float(p), float(dt), float(rtol),
+                               float(atol), C.cast(v, C.c_void_p), C.cast(C.pointer(ms), C.c_void_p), _stream()))
+    return dict(persistent=v[0], waves_per_block=v[1], grid_mult=v[2]), ms.value
+
+
+EXPORTED = ["chem_load_mechanism", "chem_free_mechanism", "chem_max_n", "chem_mech_sizes", "chem_set_arrhenius",
+            "chem_integrate", "chem_integrate_adjoint", "chem_rhs", "chem_jacobian", "chem_lu_solve",
+            "chem_autotune", "chem_last_error"]

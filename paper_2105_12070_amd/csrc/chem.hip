@@ -1,0 +1,690 @@
+// MI355X batched stiff-chemistry integrator: kernels and the C ABI of chem.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/chem.h"
+#include "chem_adjoint.hpp"
+#include "chem_cell.hpp"
+
+using namespace chem;
+
+// ===================================================================== kernels
+namespace {
+
+constexpr int MAX_WPB = 8;
+
+__device__ inline void stage_blob(uint8_t* lds, const uint8_t* blob, int bytes) {
+  const uint4* src = (const uint4*)blob;
+  uint4* dst = (uint4*)lds;
+  for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+}
+
+template <int NP>
+constexpr int max_threads() {
+  return NP <= 16 ? 64 * MAX_WPB : 256;
+}
+
+template <int NP>
+__global__ __launch_bounds__(max_threads<NP>()) void k_integrate(IntArgs a) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  stage_blob(lds, a.blob, a.d.lds_bytes);
+  const MechView m = make_view(lds, a);
+  const int wv = threadIdx.x / WAVE;
+  const CellWs w = make_ws((double*)(lds + a.d.lds_bytes) + (size_t)wv * a.cell_doubles, a.d);
+  // one call site: a persistent wave pulls cells from the queue until it is
+  // drained, a plain wave handles the one cell of its slot
+  int64_t idx;
+  if (a.queue) {
+    int v = 0;
+    if (lane_id() == 0) v = atomicAdd(a.queue, 1);
+    idx = uniform_int(__shfl(v, 0));
+  } else {
+    idx = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
+  }
+  while (idx < a.ncells) {
+    const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
+    integrate_cell<NP>(m, w, a, c);
+    if (!a.queue) break;
+    int v = 0;
+    if (lane_id() == 0) v = atomicAdd(a.queue, 1);
+    idx = uniform_int(__shfl(v, 0));
+  }
+}
+
+__global__ void k_reset(int* q) {
+  if (threadIdx.x == 0) *q = 0;
+}
+
+template <int NP>
+__global__ __launch_bounds__(max_threads<NP>()) void k_rhs_jac(IntArgs a, const double* st, double* f, double* J) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  stage_blob(lds, a.blob, a.d.lds_bytes);
+  const MechView m = make_view(lds, a);
+  const int wv = threadIdx.x / WAVE;
+  const CellWs w = make_ws((double*)(lds + a.d.lds_bytes) + (size_t)wv * a.cell_doubles, a.d);
+  const int64_t c = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
+  if (c >= a.ncells) return;
+  const int lane = lane_id();
+  const int N = m.d.N;
+  if (lane == 0) {
+    w.C[m.d.K] = 1.0;
+    w.g[m.d.K] = 0.0;
+    w.hR[m.d.K] = 0.0;
+  }
+  wsync();
+  const double y = lane < N ? st[(int64_t)lane * a.ld + c] : 0.0;
+  double row[NP];
+  double fv;
+  if (J) {
+    fv = jac_pass<NP>(m, w, y, a.p, lane, row);
+    if (lane < N)
+      for (int j = 0; j < N; ++j) J[((size_t)c * N + lane) * N + j] = w.J[lane * m.d.S + j];
+  } else {
+    fv = rhs(m, w, y, a.p, lane);
+  }
+  if (f && lane < N) f[(int64_t)lane * a.ld + c] = fv;
+}
+
+template <int NP>
+__global__ __launch_bounds__(256) void k_lu_solve(int64_t nmat, int n, const double* A, double* b, int32_t* info) {
+  const int64_t mi = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (mi >= nmat) return;
+  const int lane = lane_id();
+  double row[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) row[j] = (lane < n && j < n) ? A[((size_t)mi * n + lane) * n + j] : 0.0;
+  int mystep;
+  double myrdiag;
+  const int rc = lu_factor<NP>(row, n, lane, mystep, myrdiag);
+  if (lane == 0) info[mi] = rc;
+  if (rc) return;
+  const double bi = lane < n ? b[(size_t)mi * n + lane] : 0.0;
+  const double x = lu_solve<NP>(row, n, lane, mystep, myrdiag, bi);
+  if (lane < n) b[(size_t)mi * n + lane] = x;
+}
+
+__global__ void k_set_arrhenius(uint8_t* blob, MechDims d, const int32_t* perm, const double* lnA, const double* b,
+                                const double* th) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= d.R) return;
+  const int o = perm[r];  // internal index -> descriptor index
+  ((double*)(blob + d.o_lnA))[r] = lnA[o];
+  ((double*)(blob + d.o_b))[r] = b[o];
+  ((double*)(blob + d.o_th))[r] = th[o];
+}
+
+}  // namespace
+
+// ================================================================ host side
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(CHEM_EHIP, std::string(#x ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Variant {
+  int persistent = 1, wpb = 4, grid_mult = 1;
+};
+
+struct GraphKey {
+  std::vector<uintptr_t> v;
+  bool operator<(const GraphKey& o) const { return v < o.v; }
+};
+
+}  // namespace
+
+struct chem_mech {
+  MechDims d{};
+  int device = 0, ncu = 0, max_lds = 0;
+  uint8_t* blob = nullptr;  // device, LDS-staged part
+  double* nasa = nullptr;
+  TbEntry* tb = nullptr;
+  double* troe = nullptr;
+  int32_t* perm = nullptr;  // device: internal -> descriptor reaction index
+  std::vector<int32_t> h_perm;
+  int* queue = nullptr;     // device work cursor
+  Variant tuned;
+  bool has_tuned = false;
+  // cached graph of the persistent launch
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+  GraphKey gkey;
+  // adjoint workspace
+  void* adj_ws = nullptr;
+  size_t adj_ws_bytes = 0;
+};
+
+namespace {
+
+int np_for(int N) {
+  if (N <= 16) return 16;
+  if (N <= 32) return 32;
+  if (N <= 64) return 64;
+  return 0;
+}
+
+size_t cell_bytes(const MechDims& d) { return (size_t)cell_ws_doubles(d.N, d.S, d.R) * sizeof(double); }
+
+int max_wpb(const chem_mech* m) {
+  const size_t avail = (size_t)m->max_lds - m->d.lds_bytes;
+  int w = (int)(avail / cell_bytes(m->d));
+  return std::min(w, np_for(m->d.N) <= 16 ? MAX_WPB : 4);
+}
+
+IntArgs base_args(const chem_mech* m) {
+  IntArgs a{};
+  a.blob = m->blob;
+  a.nasa = m->nasa;
+  a.tb = m->tb;
+  a.troe = m->troe;
+  a.d = m->d;
+  a.cell_doubles = cell_ws_doubles(m->d.N, m->d.S, m->d.R);
+  return a;
+}
+
+template <class F>
+int with_np(int N, F&& f) {
+  switch (np_for(N)) {
+    case 16: return f(std::integral_constant<int, 16>());
+    case 32: return f(std::integral_constant<int, 32>());
+    case 64: return f(std::integral_constant<int, 64>());
+  }
+  return fail(CHEM_EUNSUPPORTED, "state size N = " + std::to_string(N) + " exceeds the compiled limit 64");
+}
+
+template <int NP>
+int set_lds_limit(const void* fn, size_t bytes) {
+  HIPCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return 0;
+}
+
+int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStream_t s) {
+  IntArgs a = a0;
+  const int wpb = std::max(1, std::min(v.wpb, max_wpb(m)));
+  if (wpb < 1) return fail(CHEM_EUNSUPPORTED, "mechanism workspace does not fit in LDS");
+  const size_t lds = m->d.lds_bytes + (size_t)wpb * cell_bytes(m->d);
+  return with_np(m->d.N, [&](auto npc) -> int {
+    constexpr int NP = decltype(npc)::value;
+    const void* fn = (const void*)k_integrate<NP>;
+    if (set_lds_limit<NP>(fn, lds)) return CHEM_EHIP;
+    int grid;
+    if (v.persistent) {
+      int occ = 0;
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_integrate<NP>, wpb * WAVE, lds));
+      occ = std::max(occ, 1);
+      const int64_t need = (a.ncells + wpb - 1) / wpb;
+      grid = (int)std::min<int64_t>((int64_t)m->ncu * occ * std::max(1, v.grid_mult), need);
+      a.queue = m->queue;
+      hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, m->queue);
+      HIPCHK(hipGetLastError());
+    } else {
+      a.queue = nullptr;
+      grid = (int)((a.ncells + wpb - 1) / wpb);
+    }
+    if (grid > 0) {
+      hipLaunchKernelGGL(k_integrate<NP>, dim3(grid), dim3(wpb * WAVE), lds, s, a);
+      HIPCHK(hipGetLastError());
+    }
+    return 0;
+  });
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* chem_last_error(void) { return g_err.c_str(); }
+
+int chem_max_n(void) { return 64; }
+
+int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
+  if (!desc || !out) return fail(CHEM_EINVAL, "null descriptor or output pointer");
+  *out = nullptr;
+  const int K = desc->n_species, R = desc->n_reactions;
+  if (K < 1 || R < 0) return fail(CHEM_EINVAL, "need n_species >= 1 and n_reactions >= 0");
+  if (K > 254) return fail(CHEM_EUNSUPPORTED, "more than 254 species");
+  if (!desc->W || !desc->nasa7 || (R > 0 && (!desc->rtype || !desc->reac || !desc->prod || !desc->lnA ||
+                                             !desc->b || !desc->theta)))
+    return fail(CHEM_EINVAL, "missing mechanism array");
+  const int N = K + 1;
+  for (int k = 0; k < K; ++k)
+    if (!(desc->W[k] > 0.0) || !std::isfinite(desc->W[k])) return fail(CHEM_EINVAL, "molar masses must be positive");
+  if (!finite_all(desc->nasa7, (size_t)15 * K)) return fail(CHEM_EINVAL, "non-finite NASA-7 coefficient");
+  for (int k = 0; k < K; ++k) {
+    const double* row = desc->nasa7 + 15 * k;
+    for (int i = 0; i <= 100; ++i) {
+      const double T = 200.0 + 58.0 * i;
+      const double* a = T > row[0] ? row + 8 : row + 1;
+      const double cp = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+      if (!(cp > 0.0)) return fail(CHEM_EINVAL, "cp <= 0 on [200, 6000] K for species " + std::to_string(k));
+    }
+  }
+  // reaction order: elementary, third-body, Troe (stable within each type)
+  std::vector<int> order;
+  for (int t = 0; t < 3; ++t)
+    for (int r = 0; r < R; ++r) {
+      const int ty = desc->rtype[r];
+      if (ty < 0 || ty > 2) return fail(CHEM_EINVAL, "reaction type must be 0, 1 or 2");
+      if (ty == t) order.push_back(r);
+    }
+  int R0 = 0, R1 = 0;
+  for (int r = 0; r < R; ++r) {
+    if (desc->rtype[r] == 0) ++R0;
+    if (desc->rtype[r] <= 1) ++R1;
+  }
+  if (R > R0 && !desc->eff) return fail(CHEM_EINVAL, "third-body reactions need efficiencies");
+  if (R > R1 && (!desc->troe || !desc->low)) return fail(CHEM_EINVAL, "Troe reactions need troe and low data");
+
+  MechDims d{};
+  d.K = K;
+  d.R = R;
+  d.N = N;
+  d.S = (N % 2 == 0) ? N + 1 : N + 2;  // odd stride with a padding column
+  d.R0 = R0;
+  d.R1 = R1;
+  // species -> (reaction, net nu) incidence, ascending internal reaction index
+  std::vector<std::vector<uint32_t>> inc(K);
+  std::vector<uint64_t> sp(R);
+  for (int ri = 0; ri < R; ++ri) {
+    const int r = order[ri];
+    int cnt[2] = {0, 0};
+    int slots[2][3] = {{K, K, K}, {K, K, K}};
+    std::map<int, int> nu;
+    for (int side = 0; side < 2; ++side) {
+      const int32_t* arr = (side == 0 ? desc->reac : desc->prod) + 3 * r;
+      for (int s = 0; s < 3; ++s) {
+        const int v = arr[s];
+        if (v < -1 || v >= K) return fail(CHEM_EINVAL, "species index out of range in reaction " + std::to_string(r));
+        if (v < 0) continue;
+        slots[side][cnt[side]++] = v;
+        nu[v] += side == 0 ? -1 : 1;
+      }
+    }
+    uint64_t w = 0;
+    for (int s = 0; s < 3; ++s) w |= (uint64_t)slots[0][s] << (8 * s);
+    for (int s = 0; s < 3; ++s) w |= (uint64_t)slots[1][s] << (8 * (s + 3));
+    w |= (uint64_t)cnt[0] << 48;
+    w |= (uint64_t)cnt[1] << 56;
+    sp[ri] = w;
+    for (auto& kv : nu)
+      if (kv.second != 0) inc[kv.first].push_back(((uint32_t)ri << 8) | (uint8_t)(int8_t)kv.second);
+  }
+  std::vector<int32_t> cptr(K + 1, 0);
+  std::vector<uint32_t> cent;
+  for (int k = 0; k < K; ++k) {
+    cptr[k] = (int32_t)cent.size();
+    cent.insert(cent.end(), inc[k].begin(), inc[k].end());
+  }
+  cptr[K] = (int32_t)cent.size();
+  d.L = (int)cent.size();
+  // LDS blob layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += (bytes + 15) & ~(size_t)15;
+    return (int)o;
+  };
+  d.o_lnA = take(8 * (size_t)R);
+  d.o_b = take(8 * (size_t)R);
+  d.o_th = take(8 * (size_t)R);
+  d.o_sp = take(8 * (size_t)R);
+  d.o_W = take(8 * (size_t)K);
+  d.o_iW = take(8 * (size_t)K);
+  d.o_cptr = take(4 * (size_t)(K + 1));
+  d.o_cent = take(4 * (size_t)std::max(d.L, 1));
+  d.lds_bytes = (int)off;
+  std::vector<uint8_t> blob(off, 0);
+  for (int ri = 0; ri < R; ++ri) {
+    const int r = order[ri];
+    ((double*)(blob.data() + d.o_lnA))[ri] = desc->lnA[r];
+    ((double*)(blob.data() + d.o_b))[ri] = desc->b[r];
+    ((double*)(blob.data() + d.o_th))[ri] = desc->theta[r];
+    ((uint64_t*)(blob.data() + d.o_sp))[ri] = sp[ri];
+  }
+  if (!finite_all(desc->lnA, R) || !finite_all(desc->b, R) || !finite_all(desc->theta, R))
+    return fail(CHEM_EINVAL, "non-finite Arrhenius parameter");
+  for (int k = 0; k < K; ++k) {
+    ((double*)(blob.data() + d.o_W))[k] = desc->W[k];
+    ((double*)(blob.data() + d.o_iW))[k] = 1.0 / desc->W[k];
+  }
+  std::memcpy(blob.data() + d.o_cptr, cptr.data(), 4 * cptr.size());
+  if (!cent.empty()) std::memcpy(blob.data() + d.o_cent, cent.data(), 4 * cent.size());
+  // global tables
+  std::vector<double> nasa((size_t)16 * K, 0.0);
+  for (int k = 0; k < K; ++k)
+    for (int i = 0; i < 15; ++i) nasa[16 * k + i] = desc->nasa7[15 * k + i];
+  std::vector<TbEntry> tb(std::max(R - R0, 1));
+  for (auto& e : tb) {
+    for (int q = 0; q < MAXTB; ++q) { e.sp[q] = (uint8_t)K; e.de[q] = 0.0; }
+  }
+  for (int ri = R0; ri < R; ++ri) {
+    const int r = order[ri];
+    int n = 0;
+    for (int k = 0; k < K; ++k) {
+      const double ev = desc->eff[(size_t)r * K + k];
+      if (!std::isfinite(ev)) return fail(CHEM_EINVAL, "non-finite efficiency");
+      if (ev != 1.0) {
+        if (n >= MAXTB) return fail(CHEM_EUNSUPPORTED, "more than 8 non-unit efficiencies in a reaction");
+        tb[ri - R0].sp[n] = (uint8_t)k;
+        tb[ri - R0].de[n] = ev - 1.0;
+        ++n;
+      }
+    }
+  }
+  std::vector<double> troe((size_t)TROE_STRIDE * std::max(R - R1, 1), 0.0);
+  for (int ri = R1; ri < R; ++ri) {
+    const int r = order[ri];
+    const double* t = desc->troe + 4 * r;
+    const double* lo = desc->low + 3 * r;
+    if (!(t[1] > 0.0) || !(t[2] > 0.0) || !finite_all(t, 4) || !finite_all(lo, 3))
+      return fail(CHEM_EINVAL, "Troe parameters need positive T*** and T*");
+    double* o = &troe[(size_t)TROE_STRIDE * (ri - R1)];
+    o[0] = t[0];
+    o[1] = 1.0 / t[1];
+    o[2] = 1.0 / t[2];
+    o[3] = t[3];
+    o[4] = lo[0];
+    o[5] = lo[1];
+    o[6] = lo[2];
+  }
+  chem_mech* m = new chem_mech();
+  m->d = d;
+  m->h_perm.assign(order.begin(), order.end());
+  auto cleanup = [&](int code, const std::string& msg) {
+    chem_free_mechanism(m);
+    return fail(code, msg);
+  };
+  if (hipGetDevice(&m->device) != hipSuccess) return cleanup(CHEM_EHIP, "hipGetDevice failed");
+  hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, m->device);
+  hipDeviceGetAttribute(&m->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
+  if (m->max_lds < d.lds_bytes + (int)cell_bytes(d))
+    return cleanup(CHEM_EUNSUPPORTED, "mechanism workspace needs more LDS than one workgroup has");
+  if (hipMalloc(&m->blob, blob.size()) != hipSuccess || hipMalloc(&m->nasa, 8 * nasa.size()) != hipSuccess ||
+      hipMalloc(&m->tb, sizeof(TbEntry) * tb.size()) != hipSuccess ||
+      hipMalloc(&m->troe, 8 * troe.size()) != hipSuccess ||
+      hipMalloc(&m->perm, 4 * (size_t)std::max(R, 1)) != hipSuccess || hipMalloc(&m->queue, 64) != hipSuccess)
+    return cleanup(CHEM_ENOMEM, "device allocation failed");
+  if (hipMemcpy(m->blob, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->nasa, nasa.data(), 8 * nasa.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->tb, tb.data(), sizeof(TbEntry) * tb.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->troe, troe.data(), 8 * troe.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      (R > 0 && hipMemcpy(m->perm, order.data(), 4 * (size_t)R, hipMemcpyHostToDevice) != hipSuccess))
+    return cleanup(CHEM_EHIP, "upload failed");
+  *out = m;
+  return CHEM_OK;
+}
+
+void chem_free_mechanism(chem_mech* m) {
+  if (!m) return;
+  if (m->gexec) hipGraphExecDestroy(m->gexec);
+  if (m->graph) hipGraphDestroy(m->graph);
+  if (m->cap_stream) hipStreamDestroy(m->cap_stream);
+  hipFree(m->blob);
+  hipFree(m->nasa);
+  hipFree(m->tb);
+  hipFree(m->troe);
+  hipFree(m->perm);
+  hipFree(m->queue);
+  hipFree(m->adj_ws);
+  delete m;
+}
+
+int chem_mech_sizes(const chem_mech* m, int32_t* K, int32_t* R) {
+  if (!m) return fail(CHEM_EINVAL, "null mechanism");
+  if (K) *K = m->d.K;
+  if (R) *R = m->d.R;
+  return CHEM_OK;
+}
+
+int chem_set_arrhenius(chem_mech* m, const double* lnA, const double* b, const double* theta, void* stream) {
+  if (!m || !lnA || !b || !theta) return fail(CHEM_EINVAL, "null argument");
+  if (m->d.R == 0) return CHEM_OK;
+  hipLaunchKernelGGL(k_set_arrhenius, dim3((m->d.R + 255) / 256), dim3(256), 0, (hipStream_t)stream, m->blob, m->d,
+                     m->perm, lnA, b, theta);
+  HIPCHK(hipGetLastError());
+  return CHEM_OK;
+}
+
+static int fill_common(const chem_mech* m, const chem_options* opt, IntArgs& a) {
+  chem_options o{};
+  o.method = 0;
+  o.max_steps = 100000;
+  o.fac_safe = 0.9;
+  o.fac_min = 0.2;
+  o.fac_max = 6.0;
+  o.h_min = 1e-20;
+  if (opt) o = *opt;
+  if (o.method != 0 && o.method != 1) return fail(CHEM_EINVAL, "method must be 0 (ROS4) or 1 (Rodas3)");
+  if (o.max_steps < 1 || !(o.fac_min > 0.0) || !(o.fac_max >= 1.0) || !(o.fac_safe > 0.0) || !(o.h_min >= 0.0))
+    return fail(CHEM_EINVAL, "invalid controller options");
+  a.method = o.method;
+  a.q = o.method == 1 ? 3.0 : 4.0;
+  a.ctl.max_steps = o.max_steps;
+  a.ctl.fac_safe = o.fac_safe;
+  a.ctl.fac_min = o.fac_min;
+  a.ctl.fac_max = o.fac_max;
+  a.ctl.h_min = o.h_min;
+  return 0;
+}
+
+static Variant pick_variant(const chem_mech* m, const chem_options* opt, int64_t ncells) {
+  Variant v = m->has_tuned ? m->tuned : Variant{1, max_wpb(m), 1};
+  if (opt) {
+    if (opt->persistent == 0 || opt->persistent == 1) v.persistent = opt->persistent;
+    if (opt->waves_per_block > 0) v.wpb = opt->waves_per_block;
+    if (opt->grid_mult > 0) v.grid_mult = opt->grid_mult;
+  }
+  v.wpb = std::max(1, std::min(v.wpb, max_wpb(m)));
+  (void)ncells;
+  return v;
+}
+
+int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* state, double* h, double p, double dt,
+                   double rtol, double atol, const chem_options* opt, int32_t* steps, int32_t* rejects,
+                   int32_t* status, void* stream) {
+  chem_mech* m = const_cast<chem_mech*>(mc);
+  if (!m) return fail(CHEM_EINVAL, "null mechanism");
+  if (ncells < 0 || ld < ncells) return fail(CHEM_EINVAL, "need 0 <= ncells <= ld");
+  if (ncells == 0) return CHEM_OK;
+  if (!state || !h) return fail(CHEM_EINVAL, "null state or h");
+  if (!(p > 0.0) || !(dt > 0.0) || !(rtol >= 0.0) || !(atol >= 0.0) || !std::isfinite(p) || !std::isfinite(dt))
+    return fail(CHEM_EINVAL, "need p > 0, dt > 0, rtol >= 0, atol >= 0");
+  if (ncells > (int64_t)INT32_MAX) return fail(CHEM_EUNSUPPORTED, "more than 2^31-1 cells");
+  IntArgs a = base_args(m);
+  if (fill_common(m, opt, a)) return CHEM_EINVAL;
+  a.state = state;
+  a.ld = ld;
+  a.ncells = ncells;
+  a.h = h;
+  a.p = 10.0 * p;
+  a.dt = dt;
+  a.rtol = rtol;
+  a.atol = atol;
+  a.steps = steps;
+  a.rejects = rejects;
+  a.status = status;
+  const Variant v = pick_variant(m, opt, ncells);
+  hipStream_t s = (hipStream_t)stream;
+  if (opt && opt->use_graph && v.persistent) {
+    GraphKey key;
+    key.v = {(uintptr_t)state, (uintptr_t)h, (uintptr_t)ncells, (uintptr_t)ld, (uintptr_t)steps,
+             (uintptr_t)rejects, (uintptr_t)status, (uintptr_t)s, (uintptr_t)v.wpb, (uintptr_t)v.grid_mult};
+    double dv[5] = {p, dt, rtol, atol, (double)(opt ? opt->method : 0)};
+    for (double x : dv) {
+      uint64_t u;
+      std::memcpy(&u, &x, 8);
+      key.v.push_back((uintptr_t)u);
+    }
+    if (!m->gexec || key.v != m->gkey.v) {
+      if (m->gexec) { hipGraphExecDestroy(m->gexec); m->gexec = nullptr; }
+      if (m->graph) { hipGraphDestroy(m->graph); m->graph = nullptr; }
+      // capture on the library's own stream (the legacy default stream cannot
+      // be captured), launch the instantiated graph on the caller's stream
+      if (!m->cap_stream) HIPCHK(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+      int rc = launch_integrate(m, a, v, m->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(m->cap_stream, &g);
+      if (rc) return rc;
+      if (e != hipSuccess) return fail(CHEM_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      m->graph = g;
+      HIPCHK(hipGraphInstantiate(&m->gexec, g, nullptr, nullptr, 0));
+      m->gkey = key;
+    }
+    HIPCHK(hipGraphLaunch(m->gexec, s));
+    return CHEM_OK;
+  }
+  return launch_integrate(m, a, v, s);
+}
+
+int chem_rhs(const chem_mech* m, int64_t ncells, int64_t ld, const double* state, double p, double* f,
+             void* stream) {
+  if (!m || !state || !f) return fail(CHEM_EINVAL, "null argument");
+  if (ncells < 0 || ld < ncells || !(p > 0.0)) return fail(CHEM_EINVAL, "invalid sizes or pressure");
+  if (ncells == 0) return CHEM_OK;
+  IntArgs a = base_args(m);
+  a.ld = ld;
+  a.ncells = ncells;
+  a.p = 10.0 * p;
+  const int wpb = std::max(1, std::min(4, max_wpb(m)));
+  const size_t lds = m->d.lds_bytes + (size_t)wpb * cell_bytes(m->d);
+  return with_np(m->d.N, [&](auto npc) -> int {
+    constexpr int NP = decltype(npc)::value;
+    if (set_lds_limit<NP>((const void*)k_rhs_jac<NP>, lds)) return CHEM_EHIP;
+    hipLaunchKernelGGL(k_rhs_jac<NP>, dim3((ncells + wpb - 1) / wpb), dim3(wpb * WAVE), lds, (hipStream_t)stream, a,
+                       state, f, (double*)nullptr);
+    HIPCHK(hipGetLastError());
+    return 0;
+  });
+}
+
+int chem_jacobian(const chem_mech* m, int64_t ncells, int64_t ld, const double* state, double p, double* J,
+                  double* f, void* stream) {
+  if (!m || !state || !J) return fail(CHEM_EINVAL, "null argument");
+  if (ncells < 0 || ld < ncells || !(p > 0.0)) return fail(CHEM_EINVAL, "invalid sizes or pressure");
+  if (ncells == 0) return CHEM_OK;
+  IntArgs a = base_args(m);
+  a.ld = ld;
+  a.ncells = ncells;
+  a.p = 10.0 * p;
+  const int wpb = std::max(1, std::min(4, max_wpb(m)));
+  const size_t lds = m->d.lds_bytes + (size_t)wpb * cell_bytes(m->d);
+  return with_np(m->d.N, [&](auto npc) -> int {
+    constexpr int NP = decltype(npc)::value;
+    if (set_lds_limit<NP>((const void*)k_rhs_jac<NP>, lds)) return CHEM_EHIP;
+    hipLaunchKernelGGL(k_rhs_jac<NP>, dim3((ncells + wpb - 1) / wpb), dim3(wpb * WAVE), lds, (hipStream_t)stream, a,
+                       state, f, J);
+    HIPCHK(hipGetLastError());
+    return 0;
+  });
+}
+
+int chem_lu_solve(int64_t nmat, int32_t n, const double* A, double* b, int32_t* info, void* stream) {
+  if (nmat < 0 || n < 1) return fail(CHEM_EINVAL, "need nmat >= 0 and n >= 1");
+  if (nmat == 0) return CHEM_OK;
+  if (!A || !b || !info) return fail(CHEM_EINVAL, "null argument");
+  return with_np(n, [&](auto npc) -> int {
+    constexpr int NP = decltype(npc)::value;
+    hipLaunchKernelGGL(k_lu_solve<NP>, dim3((nmat + 3) / 4), dim3(256), 0, (hipStream_t)stream, nmat, n, A, b, info);
+    HIPCHK(hipGetLastError());
+    return 0;
+  });
+}
+
+int chem_autotune(chem_mech* m, int64_t ncells, int64_t ld, const double* state, const double* h, double p,
+                  double dt, double rtol, double atol, int32_t* out_variant, double* out_ms, void* stream) {
+  if (!m || !state || !h) return fail(CHEM_EINVAL, "null argument");
+  if (ncells < 1 || ld < ncells) return fail(CHEM_EINVAL, "need 1 <= ncells <= ld");
+  const int N = m->d.N;
+  hipStream_t s = (hipStream_t)stream;
+  double *st = nullptr, *hh = nullptr;
+  if (hipMalloc(&st, sizeof(double) * N * ncells) != hipSuccess || hipMalloc(&hh, sizeof(double) * ncells) != hipSuccess) {
+    hipFree(st);
+    return fail(CHEM_ENOMEM, "autotune scratch allocation failed");
+  }
+  hipEvent_t e0, e1;
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  std::vector<Variant> cands;
+  for (int w = 1; w <= max_wpb(m); ++w) {
+    cands.push_back({0, w, 1});
+    cands.push_back({1, w, 1});
+    cands.push_back({1, w, 2});
+  }
+  Variant best = cands.front();
+  double best_ms = 1e300;
+  int rc = 0;
+  chem_options o{};
+  o.method = 0;
+  o.max_steps = 100000;
+  o.fac_safe = 0.9;
+  o.fac_min = 0.2;
+  o.fac_max = 6.0;
+  o.h_min = 1e-20;
+  for (const Variant& v : cands) {
+    o.persistent = v.persistent;
+    o.waves_per_block = v.wpb;
+    o.grid_mult = v.grid_mult;
+    double ms_best = 1e300;
+    for (int rep = 0; rep < 2 && rc == 0; ++rep) {
+      hipMemcpy2DAsync(st, sizeof(double) * ncells, state, sizeof(double) * ld, sizeof(double) * ncells, N,
+                       hipMemcpyDeviceToDevice, s);
+      hipMemcpyAsync(hh, h, sizeof(double) * ncells, hipMemcpyDeviceToDevice, s);
+      hipEventRecord(e0, s);
+      rc = chem_integrate(m, ncells, ncells, st, hh, p, dt, rtol, atol, &o, nullptr, nullptr, nullptr, s);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms_best = std::min(ms_best, (double)ms);
+    }
+    if (rc) break;
+    if (ms_best < best_ms) {
+      best_ms = ms_best;
+      best = v;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipFree(st);
+  hipFree(hh);
+  if (rc) return rc;
+  m->tuned = best;
+  m->has_tuned = true;
+  if (out_variant) {
+    out_variant[0] = best.persistent;
+    out_variant[1] = best.wpb;
+    out_variant[2] = best.grid_mult;
+  }
+  if (out_ms) *out_ms = best_ms;
+  return CHEM_OK;
+}
+
+}  // extern "C"
+
+#include "chem_adjoint_host.inc"

@@ -1,0 +1,614 @@
+// Device solver for one cell per wavefront (N <= NP <= 64).
+//
+// Layout: lane i owns component i of every state-sized vector (lane 0 = T,
+// lane 1+k = Y_k) and row i of the iteration matrix M = I/(gamma h) - J, held
+// in NP registers.  Reaction-level work runs one reaction per lane in rounds
+// of 64; species-level work runs one species per lane.  The Jacobian is
+// assembled in the wave's LDS workspace, rows owned by lanes, so its
+// accumulation is deterministic.
+#pragma once
+#include "chem_common.hpp"
+
+namespace chem {
+
+struct MechView {
+  MechDims d;
+  const double* lnA;      // LDS
+  const double* b;        // LDS
+  const double* th;       // LDS
+  const uint64_t* sp;     // LDS: reactant slots in bytes 0..2, products 3..5, n_reac byte 6, n_prod byte 7
+  const double* W;        // LDS
+  const double* iW;       // LDS
+  const int32_t* cptr;    // LDS [K+1]
+  const uint32_t* cent;   // LDS [L] (r << 8) | (uint8)nu
+  const double* nasa;     // global [K][16]
+  const TbEntry* tb;      // global [R - R0]
+  const double* troe;     // global [R - R1][8]
+};
+
+__device__ inline MechView make_view(const uint8_t* lds, const IntArgs& a) {
+  MechView m;
+  m.d = a.d;
+  m.lnA = (const double*)(lds + a.d.o_lnA);
+  m.b = (const double*)(lds + a.d.o_b);
+  m.th = (const double*)(lds + a.d.o_th);
+  m.sp = (const uint64_t*)(lds + a.d.o_sp);
+  m.W = (const double*)(lds + a.d.o_W);
+  m.iW = (const double*)(lds + a.d.o_iW);
+  m.cptr = (const int32_t*)(lds + a.d.o_cptr);
+  m.cent = (const uint32_t*)(lds + a.d.o_cent);
+  m.nasa = a.nasa;
+  m.tb = a.tb;
+  m.troe = a.troe;
+  return m;
+}
+
+// Per-wave LDS workspace.
+struct CellWs {
+  double* J;    // [N][S]
+  double* rk;   // [R] q (RHS) or k_eff (Jacobian)
+  double* rkr;  // [R] k_eff / K_c
+  double* rdm;  // [R] d q / d[M]
+  double* rdt;  // [R] d q / dT at fixed C
+  double* C;    // [64+1] concentrations, C[K] = 1 (padding species)
+  double* g;    // [64+1] g/RT (reused for mass enthalpy in the Jacobian pass)
+  double* hR;   // [64+1] h/RT
+};
+
+__host__ __device__ inline int cell_ws_doubles(int N, int S, int R) { return N * S + 4 * R + 3 * 66; }
+
+__device__ inline CellWs make_ws(double* base, const MechDims& d) {
+  CellWs w;
+  w.J = base;
+  w.rk = w.J + d.N * d.S;
+  w.rkr = w.rk + d.R;
+  w.rdm = w.rkr + d.R;
+  w.rdt = w.rdm + d.R;
+  w.C = w.rdt + d.R;
+  w.g = w.C + 66;
+  w.hR = w.g + 66;
+  return w;
+}
+
+// Uniform mixture quantities of one evaluation point.
+struct Mix {
+  double T, lnT, iT, rho, iRho, Wbar, cp, Ctot, lnPRT;
+};
+
+// Lane-local species thermo: NASA-7 cp/R, h/RT, s/R and d(cp/R)/dT.
+struct SpThermo {
+  double cpR, hRT, sR, dcpR;
+};
+
+__device__ inline SpThermo nasa7(const double* row, double T, double lnT, double iT) {
+  const double* a = (T > row[0]) ? row + 8 : row + 1;
+  SpThermo t;
+  t.cpR = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+  t.hRT = a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + T * a[4] * 0.2))) + a[5] * iT;
+  t.sR = a[0] * lnT + T * (a[1] + T * (a[2] * 0.5 + T * (a[3] * (1.0 / 3.0) + T * a[4] * 0.25))) + a[6];
+  t.dcpR = a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + T * 4.0 * a[4]));
+  return t;
+}
+
+// Species phase shared by f and J: thermo at T, mixture density, and the
+// concentrations / g/RT / h/RT the reaction lanes gather.  Returns the lane's
+// species thermo (garbage on non-species lanes).
+__device__ inline SpThermo species_phase(const MechView& m, const CellWs& w, double y, double p, int lane,
+                                         Mix& x, double& Yk) {
+  const int K = m.d.K;
+  x.T = readlane(y, 0);
+  x.lnT = log(x.T);
+  x.iT = 1.0 / x.T;
+  const bool isSp = lane >= 1 && lane <= K;
+  const int k = isSp ? lane - 1 : 0;
+  SpThermo t = nasa7(m.nasa + 16 * k, x.T, x.lnT, x.iT);
+  Yk = isSp ? y : 0.0;
+  const double iWk = m.iW[k];
+  const double yw = Yk * iWk;
+  const double sy = wave_sum(yw);
+  x.Wbar = 1.0 / sy;
+  x.rho = p * x.Wbar * x.iT / RU;
+  x.iRho = 1.0 / x.rho;
+  x.Ctot = p * x.iT / RU;
+  x.lnPRT = log(PATM * x.iT / RU);
+  x.cp = wave_sum(isSp ? Yk * t.cpR * RU * iWk : 0.0);
+  if (isSp) {
+    w.C[k] = x.rho * yw;
+    w.g[k] = t.hRT - t.sR;
+    w.hR[k] = t.hRT;
+  }
+  wsync();
+  return t;
+}
+
+// One reaction's slot data from the packed word.
+struct Slots {
+  int r0, r1, r2, p0, p1, p2, dnu;
+};
+__device__ __forceinline__ Slots unpack(uint64_t s) {
+  Slots o;
+  o.r0 = (int)(s & 0xFF);
+  o.r1 = (int)((s >> 8) & 0xFF);
+  o.r2 = (int)((s >> 16) & 0xFF);
+  o.p0 = (int)((s >> 24) & 0xFF);
+  o.p1 = (int)((s >> 32) & 0xFF);
+  o.p2 = (int)((s >> 40) & 0xFF);
+  o.dnu = (int)((s >> 56) & 0xFF) - (int)((s >> 48) & 0xFF);
+  return o;
+}
+
+__device__ __forceinline__ double third_body(const MechView& m, const CellWs& w, int r, double Ctot) {
+  const TbEntry& e = m.tb[r - m.d.R0];
+  double M = Ctot;
+#pragma unroll
+  for (int t = 0; t < MAXTB; ++t) M += e.de[t] * w.C[e.sp[t]];
+  return M;
+}
+
+// Troe falloff: k = kinf Pr/(1+Pr) F, Pr = k0 [M]/kinf.  Returns k and, when
+// Deriv, d k / d[M] / net-factor pieces and d ln k / dT.
+template <bool Deriv>
+__device__ __forceinline__ double troe_k(const MechView& m, int r, const Mix& x, double kf, double dlnkf, double M,
+                                         double& dk_dM, double& dlnk_dT) {
+  const double* t = m.troe + TROE_STRIDE * (r - m.d.R1);
+  const double alpha = t[0], iT3 = t[1], iT1 = t[2], T2 = t[3];
+  const double k0 = exp(t[4] + t[5] * x.lnT - t[6] * x.iT);
+  const double Pr = k0 * M / kf;
+  const double e3 = exp(-x.T * iT3), e1 = exp(-x.T * iT1), e2 = exp(-T2 * x.iT);
+  const double Fc = (1.0 - alpha) * e3 + alpha * e1 + e2;
+  const double xF = log10(Fc);
+  const double L = log10(Pr);
+  const double c = -0.4 - 0.67 * xF;
+  const double n = 0.75 - 1.27 * xF;
+  const double d = n - 0.14 * (L + c);
+  const double f1 = (L + c) / d;
+  const double den = 1.0 + f1 * f1;
+  const double F = exp10(xF / den);
+  const double ipr = 1.0 / (1.0 + Pr);
+  const double k = k0 * M * ipr * F;
+  if (Deriv) {
+    const double id2 = 1.0 / (d * d);
+    const double dlgF_dL = -xF * 2.0 * f1 / (den * den) * n * id2;
+    const double dlgF_dx = 1.0 / den - xF * 2.0 * f1 / (den * den) * (-0.67 * d + 1.1762 * (L + c)) * id2;
+    const double gg = ipr + dlgF_dL;
+    dk_dM = k0 * F * ipr * gg;
+    const double dFc = -(1.0 - alpha) * iT3 * e3 - alpha * iT1 * e1 + T2 * x.iT * x.iT * e2;
+    const double dlnk0 = t[5] * x.iT + t[6] * x.iT * x.iT;
+    dlnk_dT = dlnkf + gg * (dlnk0 - dlnkf) + dlgF_dx * dFc / Fc;
+  }
+  return k;
+}
+
+// f(Phi) for the wave's cell: lane i gets f_i.
+__device__ inline double rhs(const MechView& m, const CellWs& w, double y, double p, int lane) {
+  const int K = m.d.K, R = m.d.R;
+  Mix x;
+  double Yk;
+  SpThermo t = species_phase(m, w, y, p, lane, x, Yk);
+#pragma clang loop unroll(disable)
+  for (int r = lane; r < R; r += WAVE) {
+    const Slots s = unpack(m.sp[r]);
+    const double lnkf = m.lnA[r] + m.b[r] * x.lnT - m.th[r] * x.iT;
+    const double Rf = w.C[s.r0] * w.C[s.r1] * w.C[s.r2];
+    const double Rr = w.C[s.p0] * w.C[s.p1] * w.C[s.p2];
+    const double sng = w.g[s.p0] + w.g[s.p1] + w.g[s.p2] - w.g[s.r0] - w.g[s.r1] - w.g[s.r2];
+    const double kf = exp(lnkf);
+    const double iKc = exp(sng - s.dnu * x.lnPRT);  // 1/K_c
+    double q = kf * (Rf - iKc * Rr);
+    if (r >= m.d.R0) {
+      const double M = third_body(m, w, r, x.Ctot);
+      if (r < m.d.R1) {
+        q *= M;
+      } else {
+        double dk, dl;
+        q = troe_k<false>(m, r, x, kf, 0.0, M, dk, dl) * (Rf - iKc * Rr);
+      }
+    }
+    w.rk[r] = q;
+  }
+  wsync();
+  const bool isSp = lane >= 1 && lane <= K;
+  double om = 0.0;
+  if (isSp) {
+    const int k = lane - 1;
+#pragma clang loop unroll(disable)
+    for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
+      const uint32_t v = m.cent[e];
+      om += (double)(int8_t)(v & 0xFF) * w.rk[v >> 8];
+    }
+  }
+  const double Q = wave_sum(isSp ? t.hRT * om : 0.0);
+  const double fT = -RU * x.T * Q * x.iRho / x.cp;
+  wsync();
+  if (lane == 0) return fT;
+  return isSp ? m.W[lane - 1] * om * x.iRho : 0.0;
+}
+
+// Analytic Jacobian (section 2.3) into w.J and f(Phi) into the return value.
+//   J_kj = (W_k/W_j) dw_k/dC_j + W_k Wbar/(rho W_j) (w_k - s_k),  s_k = sum_i C_i dw_k/dC_i
+//   J_kT = (W_k/rho) (dw_k/dT - s_k/T + w_k/T)
+//   J_Tj = -(sum_k hm_k J_kj + f_T cpm_j)/c_p,  J_TT = -(sum_k hm_k J_kT + sum_k cpm_k f_k + f_T dc_p/dT)/c_p
+// (hm, cpm: mass-specific enthalpy and heat capacity).  `row` is scratch.
+template <int NP>
+__device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, double p, int lane,
+                                  double (&row)[NP]) {
+  const int K = m.d.K, R = m.d.R, N = m.d.N, S = m.d.S;
+  Mix x;
+  double Yk;
+  SpThermo t = species_phase(m, w, y, p, lane, x, Yk);
+#pragma clang loop unroll(disable)
+  for (int r = lane; r < R; r += WAVE) {
+    const Slots s = unpack(m.sp[r]);
+    const double lnkf = m.lnA[r] + m.b[r] * x.lnT - m.th[r] * x.iT;
+    const double Rf = w.C[s.r0] * w.C[s.r1] * w.C[s.r2];
+    const double Rr = w.C[s.p0] * w.C[s.p1] * w.C[s.p2];
+    const double sng = w.g[s.p0] + w.g[s.p1] + w.g[s.p2] - w.g[s.r0] - w.g[s.r1] - w.g[s.r2];
+    const double snh = w.hR[s.p0] + w.hR[s.p1] + w.hR[s.p2] - w.hR[s.r0] - w.hR[s.r1] - w.hR[s.r2];
+    const double kf = exp(lnkf);
+    const double iKc = exp(sng - s.dnu * x.lnPRT);
+    const double dlnkf = m.b[r] * x.iT + m.th[r] * x.iT * x.iT;
+    const double dlnKc = (snh - (double)s.dnu) * x.iT;
+    const double net = Rf - iKc * Rr;
+    double keff = kf, dkM = 0.0, dqdT;
+    if (r < m.d.R0) {
+      dqdT = kf * (dlnkf * Rf - iKc * (dlnkf - dlnKc) * Rr);
+    } else {
+      const double M = third_body(m, w, r, x.Ctot);
+      if (r < m.d.R1) {
+        keff = kf * M;
+        dkM = kf * net;
+        dqdT = M * kf * (dlnkf * Rf - iKc * (dlnkf - dlnKc) * Rr);
+      } else {
+        double dlnk;
+        keff = troe_k<true>(m, r, x, kf, dlnkf, M, dkM, dlnk);
+        dkM *= net;
+        dqdT = keff * (dlnk * net + iKc * Rr * dlnKc);
+      }
+    }
+    w.rk[r] = keff;
+    w.rkr[r] = keff * iKc;
+    w.rdm[r] = dkM;
+    w.rdt[r] = dqdT;
+  }
+  // species rows of dw/dC (sparse, lane-owned rows of J)
+  const bool isSp = lane >= 1 && lane <= K;
+  double* Jr = w.J + lane * S;
+  if (lane < N) {
+#pragma unroll
+    for (int j = 0; j < NP + 2; ++j)
+      if (j < S) Jr[j] = 0.0;
+  }
+  wsync();
+  double om = 0.0, dwdT = 0.0, adense = 0.0;
+  if (isSp) {
+    const int k = lane - 1;
+#pragma clang loop unroll(disable)
+    for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
+      const uint32_t v = m.cent[e];
+      const int r = (int)(v >> 8);
+      const double nu = (double)(int8_t)(v & 0xFF);
+      const Slots s = unpack(m.sp[r]);
+      const double c0 = w.C[s.r0], c1 = w.C[s.r1], c2 = w.C[s.r2];
+      const double d0 = w.C[s.p0], d1 = w.C[s.p1], d2 = w.C[s.p2];
+      const double kf = w.rk[r], kr = w.rkr[r];
+      om += nu * (kf * c0 * c1 * c2 - kr * d0 * d1 * d2);
+      dwdT += nu * w.rdt[r];
+      const double a = nu * kf, bb = -nu * kr;
+      atomicAdd(Jr + 1 + s.r0, a * c1 * c2);
+      atomicAdd(Jr + 1 + s.r1, a * c0 * c2);
+      atomicAdd(Jr + 1 + s.r2, a * c0 * c1);
+      atomicAdd(Jr + 1 + s.p0, bb * d1 * d2);
+      atomicAdd(Jr + 1 + s.p1, bb * d0 * d2);
+      atomicAdd(Jr + 1 + s.p2, bb * d0 * d1);
+      if (r >= m.d.R0) {
+        const double dm = nu * w.rdm[r];
+        adense += dm;
+        const TbEntry& te = m.tb[r - m.d.R0];
+#pragma unroll
+        for (int q = 0; q < MAXTB; ++q) atomicAdd(Jr + 1 + te.sp[q], dm * te.de[q]);
+      }
+    }
+  }
+  wsync();
+  // dense transform of the lane's row: rank-1 density term and W scaling
+  double fk = 0.0;
+  if (isSp) {
+    const int k = lane - 1;
+    const double Wk = m.W[k];
+    double sk = 0.0;
+#pragma unroll
+    for (int j = 1; j < NP; ++j) {
+      if (j < N) {
+        const double v = Jr[j] + adense;
+        row[j] = v;
+        sk += w.C[j - 1] * v;
+      }
+    }
+    const double gam = Wk * x.Wbar * x.iRho * (om - sk);
+#pragma unroll
+    for (int j = 1; j < NP; ++j)
+      if (j < N) Jr[j] = m.iW[j - 1] * (Wk * row[j] + gam);
+    Jr[0] = Wk * x.iRho * (dwdT - sk * x.iT + om * x.iT);
+    fk = Wk * om * x.iRho;
+    // mass-specific enthalpy for the T row (g/RT is no longer needed)
+    w.g[k] = RU * x.T * t.hRT * m.iW[k];
+  }
+  const double Q = wave_sum(isSp ? t.hRT * om : 0.0);
+  const double fT = -RU * x.T * Q * x.iRho / x.cp;
+  const double cpm = isSp ? RU * t.cpR * m.iW[lane - 1] : 0.0;
+  const double s1 = wave_sum(cpm * fk);
+  const double dcpdT = wave_sum(isSp ? Yk * RU * t.dcpR * m.iW[lane - 1] : 0.0);
+  wsync();
+  // T row: column sums of the species rows weighted by mass enthalpy
+  if (lane < N) {
+    double acc = 0.0;
+#pragma clang loop unroll(disable)
+    for (int k = 0; k < K; ++k) acc += w.g[k] * w.J[(1 + k) * S + lane];
+    w.J[lane] = (lane == 0) ? -(acc + s1 + fT * dcpdT) / x.cp : -(acc + fT * cpm) / x.cp;
+  }
+  wsync();
+  return lane == 0 ? fT : fk;
+}
+
+// LU with partial pivoting of the row-per-lane matrix.  No rows move: the
+// lane chosen at step k records mystep = k; L multipliers of step k stay in
+// column k of the remaining rows.  The pivot is the first lane whose |a|
+// carries the largest upper 32 bits (sign cleared) among unpivoted rows.
+// Steps run in static phases of four: phase P only touches columns >= 4P.
+// Inside a phase the four columns of chunk P rotate through c0..c3 so that
+// the pivot column is always c0; every register index is static.
+// Returns the 1-based step of a zero pivot, or 0.
+template <int NP>
+__device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep, double& myrdiag) {
+  mystep = lane < N ? -1 : (1 << 20);
+  myrdiag = 0.0;
+  int info = 0;
+#pragma clang loop unroll(full)
+  for (int P = 0; P < NP / 4; ++P) {
+    const int k0 = 4 * P;
+    const int k1 = min(k0 + 4, N);
+    double c0 = row[k0], c1 = row[k0 + 1], c2 = row[k0 + 2], c3 = row[k0 + 3];
+#pragma clang loop unroll(disable)
+    for (int k = k0; k < k1; ++k) {
+      const int kk = k - k0;
+      const bool elig = mystep < 0;
+      const unsigned hi = (unsigned)(__builtin_bit_cast(unsigned long long, c0) >> 32) & 0x7fffffffu;
+      const unsigned key = elig ? hi : 0u;
+      const unsigned kmax = wave_max_u32(key);
+      // a zero pivot column is recorded and the factorisation runs on with
+      // zero multipliers (no early exit keeps the control flow simple)
+      const bool sing = kmax == 0u;
+      if (sing && info == 0) info = k + 1;
+      const int p = sing ? 0 : uniform_int(__builtin_ctzll(ballot(elig && key == kmax)));
+      const double piv = readlane(c0, p);
+      const double rp = 1.0 / piv;
+      const bool upd = elig && lane != p && !sing;
+      if (lane == p && !sing) {
+        mystep = k;
+        myrdiag = rp;
+      }
+      const double l = upd ? c0 * rp : 0.0;
+      // c1..c3 hold columns k+1.. of the chunk first, then finished columns
+      double u1 = readlane(c1, p), u2 = readlane(c2, p), u3 = readlane(c3, p);
+      u1 = kk <= 2 ? u1 : 0.0;
+      u2 = kk <= 1 ? u2 : 0.0;
+      u3 = kk == 0 ? u3 : 0.0;
+      c1 = fma(-l, u1, c1);
+      c2 = fma(-l, u2, c2);
+      c3 = fma(-l, u3, c3);
+      c0 = upd ? l : c0;
+#pragma unroll
+      for (int j = k0 + 4; j < NP; ++j) row[j] = fma(-l, readlane(row[j], p), row[j]);
+      const double t = c0;
+      c0 = c1;
+      c1 = c2;
+      c2 = c3;
+      c3 = t;
+    }
+    // a short final phase re-aligns the rotation
+#pragma clang loop unroll(disable)
+    for (int r = max(k1 - k0, 0); r < 4; ++r) {
+      const double t = c0;
+      c0 = c1;
+      c1 = c2;
+      c2 = c3;
+      c3 = t;
+    }
+    row[k0] = c0;
+    row[k0 + 1] = c1;
+    row[k0 + 2] = c2;
+    row[k0 + 3] = c3;
+  }
+  return info;
+}
+
+// Solve M x = b with the factors of lu_factor; lane i holds b_i and gets x_i.
+template <int NP>
+__device__ inline double lu_solve(const double (&row)[NP], int N, int lane, int mystep, double myrdiag, double b) {
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    if (k < N) {
+      const int p = uniform_int(__builtin_ctzll(ballot(mystep == k)));
+      const double yk = readlane(b, p);
+      if (mystep > k) b = fma(-row[k], yk, b);
+    }
+  }
+  double x = 0.0;
+#pragma unroll
+  for (int k = NP - 1; k >= 0; --k) {
+    if (k < N) {
+      const int p = uniform_int(__builtin_ctzll(ballot(mystep == k)));
+      const double xk = readlane(b * myrdiag, p);
+      if (mystep < k) b = fma(-row[k], xk, b);
+      if (lane == k) x = xk;
+    }
+  }
+  return x;
+}
+
+// M = I/(gamma h) - J from the LDS Jacobian into row registers.  Returns
+// false if a row holds a non-finite value.
+template <int NP>
+__device__ inline bool form_matrix(const CellWs& w, int N, int S, int lane, double d, double (&row)[NP]) {
+  double chk = 0.0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j) row[j] = 0.0;
+  if (lane < N) {
+    double* Jr = w.J + lane * S;
+    const double jd = Jr[lane];
+    Jr[lane] = jd - d;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      if (j < N) row[j] = -Jr[j];
+      chk += row[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    Jr[lane] = jd;
+  }
+  return ballot(!__builtin_isfinite(chk)) == 0ull;
+}
+
+// One Rosenbrock attempt from y with f0 = f(y) and J(y) in LDS.  Writes ynew
+// and err (lane-local); returns 1 if M is singular and 2 if M holds a
+// non-finite value.  Stage vectors live in a shift register: after stage i,
+// K0 = K_i, K1 = K_{i-1}, ..., so coefficient a_ij multiplies K_{i-1-j}.
+template <int NP>
+__device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosTable& tab, double p, int lane,
+                                  double y, double f0, double h, double (&row)[NP], double& ynew, double& err,
+                                  int& mystep, double& myrdiag) {
+  const int N = m.d.N;
+  if (!form_matrix<NP>(w, N, m.d.S, lane, 1.0 / (tab.gamma * h), row)) return 2;
+  if (lu_factor<NP>(row, N, lane, mystep, myrdiag)) return 1;
+  const double ih = 1.0 / h;
+  const int s = tab.s;
+  double K0 = 0.0, K1 = 0.0, K2 = 0.0, K3 = 0.0;
+  double fi = f0;
+#pragma clang loop unroll(disable)
+  for (int i = 0; i < s; ++i) {
+    // contributions of K_{i-1}, K_{i-2}, K_{i-3}
+    const double a0 = i >= 1 ? tab.a[i][i - 1] : 0.0, c0 = i >= 1 ? tab.c[i][i - 1] : 0.0;
+    const double a1 = i >= 2 ? tab.a[i][i - 2] : 0.0, c1 = i >= 2 ? tab.c[i][i - 2] : 0.0;
+    const double a2 = i >= 3 ? tab.a[i][i - 3] : 0.0, c2 = i >= 3 ? tab.c[i][i - 3] : 0.0;
+    if (i > 0 && tab.newf[i]) {
+      const double Yi = y + a0 * K0 + a1 * K1 + a2 * K2;
+      fi = rhs(m, w, lane < N ? Yi : 0.0, p, lane);
+    }
+    const double r = fi + ih * (c0 * K0 + c1 * K1 + c2 * K2);
+    const double ki = lu_solve<NP>(row, N, lane, mystep, myrdiag, lane < N ? r : 0.0);
+    K3 = K2;
+    K2 = K1;
+    K1 = K0;
+    K0 = ki;
+  }
+  // after s stages K0 = K_{s-1}, K1 = K_{s-2}, ...
+  const double m0 = tab.m[s - 1], e0 = tab.e[s - 1];
+  const double m1 = s >= 2 ? tab.m[s - 2] : 0.0, e1 = s >= 2 ? tab.e[s - 2] : 0.0;
+  const double m2 = s >= 3 ? tab.m[s - 3] : 0.0, e2 = s >= 3 ? tab.e[s - 3] : 0.0;
+  const double m3 = s >= 4 ? tab.m[s - 4] : 0.0, e3 = s >= 4 ? tab.e[s - 4] : 0.0;
+  ynew = y + (m0 * K0 + m1 * K1 + m2 * K2 + m3 * K3);
+  err = e0 * K0 + e1 * K1 + e2 * K2 + e3 * K3;
+  return 0;
+}
+
+// Adaptive integration of cell c over [0, dt]; the step-size controller
+// follows the constants in a.ctl (accept iff err <= 1, no growth right after a
+// rejection, non-finite err rejects with fac_min, the last step is clipped to
+// dt and h_out is the last unclipped proposal capped at dt).
+template <int NP>
+__device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs& a, int64_t c) {
+  const int lane = lane_id();
+  const int N = m.d.N;
+  if (lane == 0) {  // padding species: C = 1, g/RT = h/RT = 0
+    w.C[m.d.K] = 1.0;
+    w.g[m.d.K] = 0.0;
+    w.hR[m.d.K] = 0.0;
+  }
+  wsync();
+  double y = lane < N ? a.state[(int64_t)lane * a.ld + c] : 0.0;
+  const double dt = a.dt;
+  const double hin = a.h[c];
+  double hprop = (__builtin_isfinite(hin) && hin > 0.0) ? fmin(hin, dt) : dt;
+  int status = ST_OK, steps = 0, rejects = 0, attempts = 0;
+  const bool bad = lane < N && (!__builtin_isfinite(y) || (lane == 0 && !(y > 0.0)));
+  if (ballot(bad)) status = ST_NONFINITE;
+  double t = 0.0;
+  bool rej_last = false;
+  double row[NP];
+  int mystep;
+  double myrdiag;
+  int ntape = 0;
+  while (status == ST_OK && t < dt) {
+    const double f0 = jac_pass<NP>(m, w, y, a.p, lane, row);
+    bool fresh = true;
+    int nsing = 0;
+    bool accepted = false;
+    while (!accepted) {
+      if (attempts >= a.ctl.max_steps) { status = ST_TOO_MANY; break; }
+      if (!(hprop >= a.ctl.h_min)) { status = ST_UNDERFLOW; break; }
+      double h = hprop;
+      bool clipped = false;
+      if (h >= dt - t) { h = dt - t; clipped = true; }
+      ++attempts;
+      if (fresh && ballot(lane < N && !__builtin_isfinite(f0))) { status = ST_NONFINITE; break; }
+      double ynew, err;
+      const int rc = ros_attempt<NP>(m, w, kTables[a.method], a.p, lane, y, f0, h, row, ynew, err, mystep, myrdiag);
+      if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
+      fresh = false;
+      if (rc) {
+        ++rejects;
+        if (++nsing > 5) { status = ST_SINGULAR; break; }
+        hprop = 0.5 * h;
+        rej_last = true;
+        continue;
+      }
+      double e = 0.0;
+      if (lane < N) {
+        const double sc = a.atol + a.rtol * fmax(fabs(y), fabs(ynew));
+        e = err / sc;
+      }
+      const double en = sqrt(wave_sum(e * e) / N);
+      const bool fin = __builtin_isfinite(en) && ballot(lane < N && !__builtin_isfinite(ynew)) == 0ull;
+      if (!fin) {
+        ++rejects;
+        hprop = a.ctl.fac_min * h;
+        rej_last = true;
+        continue;
+      }
+      const double fac = fmin(a.ctl.fac_max, fmax(a.ctl.fac_min, a.ctl.fac_safe * pow(en, -1.0 / a.q)));
+      if (uniform_int(en <= 1.0)) {
+        accepted = true;
+        ++steps;
+        if (a.tape_h) {
+          if (ntape < a.max_tape) {
+            if (lane == 0) a.tape_h[c * (int64_t)a.max_tape + ntape] = h;
+          }
+          ++ntape;
+        }
+        t = clipped ? dt : t + h;
+        y = ynew;
+        double hn = h * fac;
+        if (rej_last) hn = fmin(hn, h);
+        if (clipped) hn = fmax(hn, hprop);
+        hprop = hn;
+        rej_last = false;
+        if (a.tape_y && ntape <= a.max_tape && (ntape % a.ckpt) == 0 && lane < N)
+          a.tape_y[(c * (int64_t)(a.max_tape / a.ckpt + 1) + ntape / a.ckpt) * N + lane] = y;
+      } else {
+        ++rejects;
+        hprop = h * fac;
+        rej_last = true;
+      }
+    }
+  }
+  if (a.tape_h && ntape > a.max_tape && status == ST_OK) status = ST_TAPE;
+  if (lane < N) a.state[(int64_t)lane * a.ld + c] = y;
+  if (lane == 0) {
+    a.h[c] = fmin(hprop, dt);
+    if (a.steps) a.steps[c] = steps;
+    if (a.rejects) a.rejects[c] = rejects;
+    if (a.status) a.status[c] = status;
+  }
+}
+
+}  // namespace chem

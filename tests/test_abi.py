@@ -1,0 +1,72 @@
+"""C-ABI library checks that need no GPU: it loads, exports every symbol the
+header declares, and rejects invalid arguments before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chem.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(chem_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2105_12070_amd import chem
+    if not os.path.exists(chem.LIB_PATH):
+        from paper_2105_12070_amd import build
+        build.build()
+    return chem.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2105_12070_amd import chem
+    assert sorted(chem.EXPORTED) == names
+
+
+def test_max_n(L):
+    assert L.chem_max_n() == 64
+
+
+def test_invalid_arguments_are_rejected_on_host(L):
+    out = C.c_void_p()
+    assert L.chem_load_mechanism(None, C.byref(out)) == -1
+    assert b"null" in L.chem_last_error()
+    assert L.chem_integrate(None, 4, 4, None, None, 1e5, 1e-6, 1e-6, 1e-10, None, None, None, None, None) == -1
+    assert L.chem_lu_solve(1, 0, None, None, None, None) == -1
+
+
+def test_mechanism_validation_on_host(L):
+    from paper_2105_12070_amd import chem
+    from paper_2105_12070_amd.inputs import WORKLOADS
+    m = WORKLOADS["c1_10sp"].mechanism()
+    bad = dict(m)
+    bad["W"] = m["W"].copy()
+    bad["W"][3] = -1.0
+    with pytest.raises(chem.ChemError, match="EINVAL"):
+        chem.Mechanism(bad)
+    bad = dict(m)
+    bad["reac"] = m["reac"].copy()
+    bad["reac"][0, 0] = 99
+    with pytest.raises(chem.ChemError, match="EINVAL"):
+        chem.Mechanism(bad)
+    bad = dict(m)
+    bad["nasa7"] = m["nasa7"].copy()
+    bad["nasa7"][2, 1:8] = [-5.0, 0, 0, 0, 0, 0, 0]
+    bad["nasa7"][2, 8:15] = [-5.0, 0, 0, 0, 0, 0, 0]
+    with pytest.raises(chem.ChemError, match="cp <= 0"):
+        chem.Mechanism(bad)
+    big = dict(m)
+    big["n_species"] = 300
+    with pytest.raises(chem.ChemError, match="EUNSUPPORTED"):
+        chem.Mechanism(big)
