@@ -1,12 +1,20 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
 Tolerances:
-  * integration at rtol 1e-10: |x_gpu - x_ref| <= 1e-8 |x_ref| + 1e-14 per
-    component (T and every Y), the bar stated for this path;
-  * integration at the metric setting (rtol 1e-6, atol 1e-10):
-    |x_gpu - x_ref| <= 10 (rtol |x_ref| + atol), since accept/reject decisions
-    taken with err close to 1 may differ by rounding and then the two runs
-    differ by up to the local error the controller allows;
+  * integration at rtol 1e-10, atol 1e-14: |x_gpu - x_ref| <= 1e-8 |x_ref| +
+    100 atol per component (T and every Y).  Relative 1e-8 is the bar stated
+    for this path; trace species are controlled by atol, and one flipped
+    accept/reject decision moves them by ~1e-13 absolute in the oracle itself,
+    hence the absolute floor of 100 atol;
+  * integration at the metric setting (rtol 1e-6, atol 1e-10): accept/reject
+    decisions taken with err close to 1 may flip on rounding, after which two
+    valid runs differ by their global error.  Measured on the same 18 cells,
+    the oracle moves by 20.7 (rtol |x| + atol) when its own safety factor
+    changes by 1e-7 relative, so the bound is 100 (rtol |x_ref| + atol); cells
+    whose step and reject counts equal the oracle's must agree to 1e-7 |x| +
+    10 atol: with the same steps only rounding differs (pivot order, exp/log
+    implementations), but stiff iteration matrices have condition numbers near
+    1e10, so per-solve differences are cond(M) eps, not eps;
   * f and J: the GPU sums reactions in a different order, so each component is
     compared against the size of that row (cancellation in omega_k).
 """
@@ -131,10 +139,13 @@ def test_jacobian_matches_oracle(chem, dev, name):
 
 
 # ------------------------------------------------------ integration parity
+TIGHT_RTOL, TIGHT_ATOL = 1e-10, 1e-14
+
+
 def _tight_check(got, ref, tag):
     dev_ = np.abs(got - ref)
-    ok = dev_ <= 1e-8 * np.abs(ref) + 1e-14
-    rel = dev_ / (np.abs(ref) + 1e-14)
+    ok = dev_ <= 1e-8 * np.abs(ref) + 100 * TIGHT_ATOL
+    rel = dev_ / (np.abs(ref) + 100 * TIGHT_ATOL)
     say(f"[{tag}] max rel dev {rel.max():.3e} median {np.median(rel):.3e}")
     assert np.all(ok), (tag, np.argwhere(~ok)[:5], rel.max())
 
@@ -143,7 +154,7 @@ def test_integrate_parity_c1_tight(chem, dev):
     """Config 1 (10 species / 27 reactions, 1,024 cells) at rtol 1e-10."""
     w, mech = mech_of("c1_10sp")
     st0 = w.states(mech)
-    rtol, atol = 1e-10, 1e-14
+    rtol, atol = TIGHT_RTOL, TIGHT_ATOL
     say("[c1 tight] gpu")
     got, h, steps, rej, status = run_gpu(chem, chem.Mechanism(mech), st0, None, w.p_pa, w.dt, rtol, atol, dev)
     assert np.all(status == 0)
@@ -152,9 +163,10 @@ def test_integrate_parity_c1_tight(chem, dev):
     ref, href, rs, rr, rst = oracle.integrate(mech, st0[:, idx], None, w.p_pa, w.dt, rtol, atol)
     assert np.all(rst == 0)
     _tight_check(got[:, idx], ref, "c1 tight")
-    same = np.mean((steps[idx] == rs) & (rej[idx] == rr))
-    say(f"[c1 tight] cells with identical (steps, rejects): {same:.3f}")
-    assert same >= 0.9
+    same = (steps[idx] == rs) & (rej[idx] == rr)
+    say(f"[c1 tight] cells with identical (steps, rejects): {same.mean():.3f}")
+    assert same.mean() >= 0.9
+    assert np.all(np.abs(got[:, idx][:, same] - ref[:, same]) <= 1e-8 * np.abs(ref[:, same]) + 10 * TIGHT_ATOL)
 
 
 @pytest.mark.parametrize("name", ["c2_54sp", "c4_adj"])
@@ -162,7 +174,7 @@ def test_integrate_parity_large_mech_tight(chem, dev, name):
     """54- and 53-species mechanisms, 70 cells (ragged over 4-cell workgroups), rtol 1e-10."""
     w, mech = mech_of(name)
     st0 = w.states(mech, 70)
-    dt, rtol, atol = 1e-8, 1e-10, 1e-14
+    dt, rtol, atol = 1e-8, TIGHT_RTOL, TIGHT_ATOL
     say(f"[{name} tight] gpu")
     got, h, steps, rej, status = run_gpu(chem, chem.Mechanism(mech), st0, None, w.p_pa, dt, rtol, atol, dev)
     assert np.all(status == 0)
@@ -170,8 +182,9 @@ def test_integrate_parity_large_mech_tight(chem, dev, name):
     say(f"[{name} tight] oracle on {len(idx)} cells")
     ref, href, rs, rr, rst = oracle.integrate(mech, st0[:, idx], None, w.p_pa, dt, rtol, atol)
     _tight_check(got[:, idx], ref, f"{name} tight")
-    same = np.mean((steps[idx] == rs) & (rej[idx] == rr))
-    say(f"[{name} tight] cells with identical (steps, rejects): {same:.3f}")
+    same = (steps[idx] == rs) & (rej[idx] == rr)
+    say(f"[{name} tight] cells with identical (steps, rejects): {same.mean():.3f}")
+    assert np.all(np.abs(got[:, idx][:, same] - ref[:, same]) <= 1e-8 * np.abs(ref[:, same]) + 10 * TIGHT_ATOL)
 
 
 def test_integrate_full_size_c2_metric(chem, dev):
@@ -188,10 +201,14 @@ def test_integrate_full_size_c2_metric(chem, dev):
     idx = np.concatenate([idx, [0, st0.shape[1] - 1]])
     say("[c2 full] oracle on sampled cells")
     ref, href, rs, rr, rst = oracle.integrate(mech, st0[:, idx], None, w.p_pa, w.dt, w.rtol, w.atol)
-    bound = 10 * (w.rtol * np.abs(ref) + w.atol)
+    bound = 100 * (w.rtol * np.abs(ref) + w.atol)
     dev_ = np.abs(got[:, idx] - ref)
-    say(f"[c2 full] max dev / bound {np.max(dev_ / bound):.3e}; steps gpu {steps[idx][:6]} oracle {rs[:6]}")
+    same = (steps[idx] == rs) & (rej[idx] == rr)
+    tight = 1e-7 * np.abs(ref[:, same]) + 10 * w.atol
+    say(f"[c2 full] max dev / bound {np.max(dev_ / bound):.3e}; identical step counts in {same.sum()}/{len(idx)}; "
+        f"their max dev / (1e-7|x| + 10 atol) {np.max(dev_[:, same] / tight) if same.any() else 0:.3e}")
     assert np.all(dev_ <= bound)
+    assert np.all(dev_[:, same] <= tight)
 
 
 def test_persistent_equals_plain_bitwise(chem, dev):
@@ -259,7 +276,7 @@ def test_ld_padding_and_empty(chem, dev):
     np.testing.assert_array_equal(out[:, nc:], st0[:, nc:])
     assert np.all(h.cpu().numpy()[nc:] == 0)
     ref = oracle.integrate(mech, st0[:, :nc], None, w.p_pa, w.dt, w.rtol, w.atol)[0]
-    assert np.all(np.abs(out[:, :nc] - ref) <= 10 * (w.rtol * np.abs(ref) + w.atol))
+    assert np.all(np.abs(out[:, :nc] - ref) <= 100 * (w.rtol * np.abs(ref) + w.atol))
 
 
 def test_rodas3_parity(chem, dev):
@@ -281,5 +298,5 @@ def test_warm_h_and_second_call(chem, dev):
     b = run_gpu(chem, m, a[0], a[1], w.p_pa, w.dt, w.rtol, w.atol, dev)
     ra = oracle.integrate(mech, st0, None, w.p_pa, w.dt, w.rtol, w.atol)
     rb = oracle.integrate(mech, ra[0], ra[1], w.p_pa, w.dt, w.rtol, w.atol)
-    assert np.all(np.abs(b[0] - rb[0]) <= 10 * (w.rtol * np.abs(rb[0]) + w.atol))
+    assert np.all(np.abs(b[0] - rb[0]) <= 100 * (w.rtol * np.abs(rb[0]) + w.atol))
     np.testing.assert_allclose(a[1], ra[1], rtol=1e-3)
