@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--graph", action="store_true", help="launch through the cached hipGraph")
+    ap.add_argument("--cells", type=int, default=0, help="integrate only the first CELLS cells (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the cells are independent, and the multi-GPU "
@@ -99,6 +100,8 @@ def main():
     w = WORKLOADS[args.config]
     mech = w.mechanism()
     st0_np = w.states(mech)
+    if args.cells:
+        st0_np = np.ascontiguousarray(st0_np[:, :args.cells])
     dev = torch.device("cuda:0")
     m = chem.Mechanism(mech)
     nc = st0_np.shape[1]

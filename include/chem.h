@@ -79,6 +79,9 @@ typedef struct chem_options {
   int32_t grid_mult;  /* persistent grid = CUs x grid_mult workgroups, 0 = auto [0] */
   int32_t cost_order; /* 1: the queue hands out cells by descending previous step count [0] */
   int32_t use_graph;  /* 1: launch the reset + integrate sequence as a cached hipGraph [0] */
+  uint64_t* phase_cycles; /* NULL [NULL], or device [ncells][8] shader-clock cycles per cell:
+                             Jacobian pass, forming M, LU, stage f, solves, total, and the
+                             reaction and species parts of the Jacobian pass */
 } chem_options;
 
 /* Validates (element balance is not required; indices, cp > 0 on

@@ -32,7 +32,7 @@ constexpr int max_threads() {
   return NP <= 16 ? 64 * MAX_WPB : 256;
 }
 
-template <int NP>
+template <int NP, bool PROF>
 __global__ __launch_bounds__(max_threads<NP>()) void k_integrate(IntArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
   stage_blob(lds, a.blob, a.d.lds_bytes);
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(max_threads<NP>()) void k_integrate(IntArgs a) {
   }
   while (idx < a.ncells) {
     const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
-    integrate_cell<NP>(m, w, a, c);
+    integrate_cell<NP, PROF>(m, w, a, c);
     if (!a.queue) break;
     int v = 0;
     if (lane_id() == 0) v = atomicAdd(a.queue, 1);
@@ -95,7 +95,10 @@ __global__ __launch_bounds__(max_threads<NP>()) void k_rhs_jac(IntArgs a, const 
 
 template <int NP>
 __global__ __launch_bounds__(256) void k_lu_solve(int64_t nmat, int n, const double* A, double* b, int32_t* info) {
-  const int64_t mi = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  __shared__ double bcast[4][64];
+  __shared__ int slots[4][64];
+  const int wv = threadIdx.x / WAVE;
+  const int64_t mi = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
   if (mi >= nmat) return;
   const int lane = lane_id();
   double row[NP];
@@ -103,11 +106,12 @@ __global__ __launch_bounds__(256) void k_lu_solve(int64_t nmat, int n, const dou
   for (int j = 0; j < NP; ++j) row[j] = (lane < n && j < n) ? A[((size_t)mi * n + lane) * n + j] : 0.0;
   int mystep;
   double myrdiag;
-  const int rc = lu_factor<NP>(row, n, lane, mystep, myrdiag);
+  const int rc = lu_factor<NP>(row, n, lane, mystep, myrdiag, bcast[wv]);
   if (lane == 0) info[mi] = rc;
   if (rc) return;
+  const int src = permute_rows<NP>(row, n, lane, mystep, myrdiag, slots[wv]);
   const double bi = lane < n ? b[(size_t)mi * n + lane] : 0.0;
-  const double x = lu_solve<NP>(row, n, lane, mystep, myrdiag, bi);
+  const double x = lu_solve<NP>(row, n, lane, src, myrdiag, bi);
   if (lane < n) b[(size_t)mi * n + lane] = x;
 }
 
@@ -155,8 +159,6 @@ struct chem_mech {
   int device = 0, ncu = 0, max_lds = 0;
   uint8_t* blob = nullptr;  // device, LDS-staged part
   double* nasa = nullptr;
-  TbEntry* tb = nullptr;
-  double* troe = nullptr;
   int32_t* perm = nullptr;  // device: internal -> descriptor reaction index
   std::vector<int32_t> h_perm;
   int* queue = nullptr;     // device work cursor
@@ -177,6 +179,7 @@ namespace {
 int np_for(int N) {
   if (N <= 16) return 16;
   if (N <= 32) return 32;
+  if (N <= 56) return 56;
   if (N <= 64) return 64;
   return 0;
 }
@@ -193,8 +196,6 @@ IntArgs base_args(const chem_mech* m) {
   IntArgs a{};
   a.blob = m->blob;
   a.nasa = m->nasa;
-  a.tb = m->tb;
-  a.troe = m->troe;
   a.d = m->d;
   a.cell_doubles = cell_ws_doubles(m->d.N, m->d.S, m->d.R);
   return a;
@@ -205,6 +206,7 @@ int with_np(int N, F&& f) {
   switch (np_for(N)) {
     case 16: return f(std::integral_constant<int, 16>());
     case 32: return f(std::integral_constant<int, 32>());
+    case 56: return f(std::integral_constant<int, 56>());
     case 64: return f(std::integral_constant<int, 64>());
   }
   return fail(CHEM_EUNSUPPORTED, "state size N = " + std::to_string(N) + " exceeds the compiled limit 64");
@@ -223,12 +225,13 @@ int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStrea
   const size_t lds = m->d.lds_bytes + (size_t)wpb * cell_bytes(m->d);
   return with_np(m->d.N, [&](auto npc) -> int {
     constexpr int NP = decltype(npc)::value;
-    const void* fn = (const void*)k_integrate<NP>;
+    auto kern = a.prof ? k_integrate<NP, true> : k_integrate<NP, false>;
+    const void* fn = (const void*)kern;
     if (set_lds_limit<NP>(fn, lds)) return CHEM_EHIP;
     int grid;
     if (v.persistent) {
       int occ = 0;
-      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_integrate<NP>, wpb * WAVE, lds));
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, wpb * WAVE, lds));
       occ = std::max(occ, 1);
       const int64_t need = (a.ncells + wpb - 1) / wpb;
       grid = (int)std::min<int64_t>((int64_t)m->ncu * occ * std::max(1, v.grid_mult), need);
@@ -240,7 +243,7 @@ int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStrea
       grid = (int)((a.ncells + wpb - 1) / wpb);
     }
     if (grid > 0) {
-      hipLaunchKernelGGL(k_integrate<NP>, dim3(grid), dim3(wpb * WAVE), lds, s, a);
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(wpb * WAVE), lds, s, a);
       HIPCHK(hipGetLastError());
     }
     return 0;
@@ -272,6 +275,7 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
                                              !desc->b || !desc->theta)))
     return fail(CHEM_EINVAL, "missing mechanism array");
   const int N = K + 1;
+  if (np_for(N) == 0) return fail(CHEM_EUNSUPPORTED, "state size N = " + std::to_string(N) + " exceeds the compiled limit 64");
   for (int k = 0; k < K; ++k)
     if (!(desc->W[k] > 0.0) || !std::isfinite(desc->W[k])) return fail(CHEM_EINVAL, "molar masses must be positive");
   if (!finite_all(desc->nasa7, (size_t)15 * K)) return fail(CHEM_EINVAL, "non-finite NASA-7 coefficient");
@@ -304,7 +308,7 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   d.K = K;
   d.R = R;
   d.N = N;
-  d.S = (N % 2 == 0) ? N + 1 : N + 2;  // odd stride with a padding column
+  d.S = np_for(N) + 1;  // odd (NP is a multiple of 8), with padding columns after N
   d.R0 = R0;
   d.R1 = R1;
   // species -> (reaction, net nu) incidence, ascending internal reaction index
@@ -342,6 +346,39 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   }
   cptr[K] = (int32_t)cent.size();
   d.L = (int)cent.size();
+  // third-body lists (non-unit efficiencies) and Troe data, internal order
+  std::vector<int32_t> tbp(R - R0 + 1, 0), tbs;
+  std::vector<double> tbd;
+  for (int ri = R0; ri < R; ++ri) {
+    const int r = order[ri];
+    int n = 0;
+    for (int k = 0; k < K; ++k) {
+      const double ev = desc->eff[(size_t)r * K + k];
+      if (!std::isfinite(ev)) return fail(CHEM_EINVAL, "non-finite efficiency");
+      if (ev != 1.0) {
+        if (++n > MAXTB) return fail(CHEM_EUNSUPPORTED, "more than 8 non-unit efficiencies in a reaction");
+        tbs.push_back(k);
+        tbd.push_back(ev - 1.0);
+      }
+    }
+    tbp[ri - R0 + 1] = (int32_t)tbs.size();
+  }
+  std::vector<double> troe((size_t)TROE_STRIDE * (R - R1), 0.0);
+  for (int ri = R1; ri < R; ++ri) {
+    const int r = order[ri];
+    const double* t = desc->troe + 4 * r;
+    const double* lo = desc->low + 3 * r;
+    if (!(t[1] > 0.0) || !(t[2] > 0.0) || !finite_all(t, 4) || !finite_all(lo, 3))
+      return fail(CHEM_EINVAL, "Troe parameters need positive T*** and T*");
+    double* o = &troe[(size_t)TROE_STRIDE * (ri - R1)];
+    o[0] = t[0];
+    o[1] = 1.0 / t[1];
+    o[2] = 1.0 / t[2];
+    o[3] = t[3];
+    o[4] = lo[0];
+    o[5] = lo[1];
+    o[6] = lo[2];
+  }
   // LDS blob layout
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -357,6 +394,10 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   d.o_iW = take(8 * (size_t)K);
   d.o_cptr = take(4 * (size_t)(K + 1));
   d.o_cent = take(4 * (size_t)std::max(d.L, 1));
+  d.o_tbp = take(4 * tbp.size());
+  d.o_tbs = take(4 * std::max<size_t>(tbs.size(), 1));
+  d.o_tbd = take(8 * std::max<size_t>(tbd.size(), 1));
+  d.o_troe = take(8 * std::max<size_t>(troe.size(), 1));
   d.lds_bytes = (int)off;
   std::vector<uint8_t> blob(off, 0);
   for (int ri = 0; ri < R; ++ri) {
@@ -374,44 +415,13 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   }
   std::memcpy(blob.data() + d.o_cptr, cptr.data(), 4 * cptr.size());
   if (!cent.empty()) std::memcpy(blob.data() + d.o_cent, cent.data(), 4 * cent.size());
-  // global tables
+  std::memcpy(blob.data() + d.o_tbp, tbp.data(), 4 * tbp.size());
+  if (!tbs.empty()) std::memcpy(blob.data() + d.o_tbs, tbs.data(), 4 * tbs.size());
+  if (!tbd.empty()) std::memcpy(blob.data() + d.o_tbd, tbd.data(), 8 * tbd.size());
+  if (!troe.empty()) std::memcpy(blob.data() + d.o_troe, troe.data(), 8 * troe.size());
   std::vector<double> nasa((size_t)16 * K, 0.0);
   for (int k = 0; k < K; ++k)
     for (int i = 0; i < 15; ++i) nasa[16 * k + i] = desc->nasa7[15 * k + i];
-  std::vector<TbEntry> tb(std::max(R - R0, 1));
-  for (auto& e : tb) {
-    for (int q = 0; q < MAXTB; ++q) { e.sp[q] = (uint8_t)K; e.de[q] = 0.0; }
-  }
-  for (int ri = R0; ri < R; ++ri) {
-    const int r = order[ri];
-    int n = 0;
-    for (int k = 0; k < K; ++k) {
-      const double ev = desc->eff[(size_t)r * K + k];
-      if (!std::isfinite(ev)) return fail(CHEM_EINVAL, "non-finite efficiency");
-      if (ev != 1.0) {
-        if (n >= MAXTB) return fail(CHEM_EUNSUPPORTED, "more than 8 non-unit efficiencies in a reaction");
-        tb[ri - R0].sp[n] = (uint8_t)k;
-        tb[ri - R0].de[n] = ev - 1.0;
-        ++n;
-      }
-    }
-  }
-  std::vector<double> troe((size_t)TROE_STRIDE * std::max(R - R1, 1), 0.0);
-  for (int ri = R1; ri < R; ++ri) {
-    const int r = order[ri];
-    const double* t = desc->troe + 4 * r;
-    const double* lo = desc->low + 3 * r;
-    if (!(t[1] > 0.0) || !(t[2] > 0.0) || !finite_all(t, 4) || !finite_all(lo, 3))
-      return fail(CHEM_EINVAL, "Troe parameters need positive T*** and T*");
-    double* o = &troe[(size_t)TROE_STRIDE * (ri - R1)];
-    o[0] = t[0];
-    o[1] = 1.0 / t[1];
-    o[2] = 1.0 / t[2];
-    o[3] = t[3];
-    o[4] = lo[0];
-    o[5] = lo[1];
-    o[6] = lo[2];
-  }
   chem_mech* m = new chem_mech();
   m->d = d;
   m->h_perm.assign(order.begin(), order.end());
@@ -425,14 +435,10 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   if (m->max_lds < d.lds_bytes + (int)cell_bytes(d))
     return cleanup(CHEM_EUNSUPPORTED, "mechanism workspace needs more LDS than one workgroup has");
   if (hipMalloc(&m->blob, blob.size()) != hipSuccess || hipMalloc(&m->nasa, 8 * nasa.size()) != hipSuccess ||
-      hipMalloc(&m->tb, sizeof(TbEntry) * tb.size()) != hipSuccess ||
-      hipMalloc(&m->troe, 8 * troe.size()) != hipSuccess ||
       hipMalloc(&m->perm, 4 * (size_t)std::max(R, 1)) != hipSuccess || hipMalloc(&m->queue, 64) != hipSuccess)
     return cleanup(CHEM_ENOMEM, "device allocation failed");
   if (hipMemcpy(m->blob, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->nasa, nasa.data(), 8 * nasa.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(m->tb, tb.data(), sizeof(TbEntry) * tb.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(m->troe, troe.data(), 8 * troe.size(), hipMemcpyHostToDevice) != hipSuccess ||
       (R > 0 && hipMemcpy(m->perm, order.data(), 4 * (size_t)R, hipMemcpyHostToDevice) != hipSuccess))
     return cleanup(CHEM_EHIP, "upload failed");
   *out = m;
@@ -446,8 +452,6 @@ void chem_free_mechanism(chem_mech* m) {
   if (m->cap_stream) hipStreamDestroy(m->cap_stream);
   hipFree(m->blob);
   hipFree(m->nasa);
-  hipFree(m->tb);
-  hipFree(m->troe);
   hipFree(m->perm);
   hipFree(m->queue);
   hipFree(m->adj_ws);
@@ -528,6 +532,7 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
   a.steps = steps;
   a.rejects = rejects;
   a.status = status;
+  a.prof = opt ? (unsigned long long*)opt->phase_cycles : nullptr;
   const Variant v = pick_variant(m, opt, ncells);
   hipStream_t s = (hipStream_t)stream;
   if (opt && opt->use_graph && v.persistent) {

@@ -9,6 +9,10 @@
 #pragma once
 #include "chem_common.hpp"
 
+#ifndef CHEM_LU_BCAST_LDS
+#define CHEM_LU_BCAST_LDS 0
+#endif
+
 namespace chem {
 
 struct MechView {
@@ -21,9 +25,11 @@ struct MechView {
   const double* iW;       // LDS
   const int32_t* cptr;    // LDS [K+1]
   const uint32_t* cent;   // LDS [L] (r << 8) | (uint8)nu
+  const int32_t* tbp;     // LDS [R - R0 + 1]
+  const int32_t* tbs;     // LDS third-body species
+  const double* tbd;      // LDS efficiency - 1
+  const double* troe;     // LDS [R - R1][8]
   const double* nasa;     // global [K][16]
-  const TbEntry* tb;      // global [R - R0]
-  const double* troe;     // global [R - R1][8]
 };
 
 __device__ inline MechView make_view(const uint8_t* lds, const IntArgs& a) {
@@ -37,9 +43,11 @@ __device__ inline MechView make_view(const uint8_t* lds, const IntArgs& a) {
   m.iW = (const double*)(lds + a.d.o_iW);
   m.cptr = (const int32_t*)(lds + a.d.o_cptr);
   m.cent = (const uint32_t*)(lds + a.d.o_cent);
+  m.tbp = (const int32_t*)(lds + a.d.o_tbp);
+  m.tbs = (const int32_t*)(lds + a.d.o_tbs);
+  m.tbd = (const double*)(lds + a.d.o_tbd);
+  m.troe = (const double*)(lds + a.d.o_troe);
   m.nasa = a.nasa;
-  m.tb = a.tb;
-  m.troe = a.troe;
   return m;
 }
 
@@ -53,9 +61,13 @@ struct CellWs {
   double* C;    // [64+1] concentrations, C[K] = 1 (padding species)
   double* g;    // [64+1] g/RT (reused for mass enthalpy in the Jacobian pass)
   double* hR;   // [64+1] h/RT
+  double* bc;   // [64] pivot-row broadcast buffer of the LU
+  int* slot;    // [64] row permutation scratch
 };
 
-__host__ __device__ inline int cell_ws_doubles(int N, int S, int R) { return N * S + 4 * R + 3 * 66; }
+// S = NP + 1, so reads of static columns j < NP + 1 from any row stay inside
+// the J block (its last row is followed by the reaction arrays).
+__host__ __device__ inline int cell_ws_doubles(int N, int S, int R) { return N * S + 4 * R + 3 * 66 + 64 + 32; }
 
 __device__ inline CellWs make_ws(double* base, const MechDims& d) {
   CellWs w;
@@ -67,6 +79,8 @@ __device__ inline CellWs make_ws(double* base, const MechDims& d) {
   w.C = w.rdt + d.R;
   w.g = w.C + 66;
   w.hR = w.g + 66;
+  w.bc = w.hR + 66;
+  w.slot = (int*)(w.bc + 64);
   return w;
 }
 
@@ -75,13 +89,47 @@ struct Mix {
   double T, lnT, iT, rho, iRho, Wbar, cp, Ctot, lnPRT;
 };
 
+// Per-phase cycle counters of one wave (compiled in only when PROF is true):
+// 0 Jacobian pass (with f(y_n)), 1 forming M, 2 LU, 3 stage f evaluations,
+// 4 triangular solves, 5 everything, 6 and 7 the reaction and species parts
+// of the Jacobian pass.
+template <bool PROF>
+struct Prof {
+  unsigned long long c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  unsigned long long t = 0;
+  __device__ __forceinline__ void start() {
+    if (PROF) t = __builtin_readcyclecounter();
+  }
+  __device__ __forceinline__ void add(int i, unsigned long long since) {
+    if (PROF) c[i] += __builtin_readcyclecounter() - since;
+  }
+  __device__ __forceinline__ unsigned long long now() const { return PROF ? __builtin_readcyclecounter() : 0ull; }
+  __device__ __forceinline__ void stop(int i) {
+    if (PROF) {
+      const unsigned long long n = __builtin_readcyclecounter();
+      c[i] += n - t;
+      t = n;
+    }
+  }
+};
+
 // Lane-local species thermo: NASA-7 cp/R, h/RT, s/R and d(cp/R)/dT.
 struct SpThermo {
   double cpR, hRT, sR, dcpR;
 };
 
 __device__ inline SpThermo nasa7(const double* row, double T, double lnT, double iT) {
-  const double* a = (T > row[0]) ? row + 8 : row + 1;
+  // both ranges are loaded before T is known, so the loads overlap the log
+  double lo[7], hi[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    lo[i] = row[1 + i];
+    hi[i] = row[8 + i];
+  }
+  const bool high = T > row[0];
+  double a[7];
+#pragma unroll
+  for (int i = 0; i < 7; ++i) a[i] = high ? hi[i] : lo[i];
   SpThermo t;
   t.cpR = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
   t.hRT = a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + T * a[4] * 0.2))) + a[5] * iT;
@@ -96,11 +144,11 @@ __device__ inline SpThermo nasa7(const double* row, double T, double lnT, double
 __device__ inline SpThermo species_phase(const MechView& m, const CellWs& w, double y, double p, int lane,
                                          Mix& x, double& Yk) {
   const int K = m.d.K;
+  const bool isSp = lane >= 1 && lane <= K;
+  const int k = isSp ? lane - 1 : 0;
   x.T = readlane(y, 0);
   x.lnT = log(x.T);
   x.iT = 1.0 / x.T;
-  const bool isSp = lane >= 1 && lane <= K;
-  const int k = isSp ? lane - 1 : 0;
   SpThermo t = nasa7(m.nasa + 16 * k, x.T, x.lnT, x.iT);
   Yk = isSp ? y : 0.0;
   const double iWk = m.iW[k];
@@ -138,10 +186,10 @@ __device__ __forceinline__ Slots unpack(uint64_t s) {
 }
 
 __device__ __forceinline__ double third_body(const MechView& m, const CellWs& w, int r, double Ctot) {
-  const TbEntry& e = m.tb[r - m.d.R0];
   double M = Ctot;
-#pragma unroll
-  for (int t = 0; t < MAXTB; ++t) M += e.de[t] * w.C[e.sp[t]];
+  const int e1 = m.tbp[r - m.d.R0 + 1];
+#pragma clang loop unroll(disable)
+  for (int e = m.tbp[r - m.d.R0]; e < e1; ++e) M += m.tbd[e] * w.C[m.tbs[e]];
   return M;
 }
 
@@ -229,10 +277,11 @@ __device__ inline double rhs(const MechView& m, const CellWs& w, double y, doubl
 //   J_kT = (W_k/rho) (dw_k/dT - s_k/T + w_k/T)
 //   J_Tj = -(sum_k hm_k J_kj + f_T cpm_j)/c_p,  J_TT = -(sum_k hm_k J_kT + sum_k cpm_k f_k + f_T dc_p/dT)/c_p
 // (hm, cpm: mass-specific enthalpy and heat capacity).  `row` is scratch.
-template <int NP>
+template <int NP, bool PROF = false>
 __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, double p, int lane,
-                                  double (&row)[NP]) {
+                                  double (&row)[NP], Prof<PROF>* pf = nullptr) {
   const int K = m.d.K, R = m.d.R, N = m.d.N, S = m.d.S;
+  const unsigned long long t0 = PROF ? pf->now() : 0ull;
   Mix x;
   double Yk;
   SpThermo t = species_phase(m, w, y, p, lane, x, Yk);
@@ -270,13 +319,14 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
     w.rdm[r] = dkM;
     w.rdt[r] = dqdT;
   }
+  if (PROF) pf->add(6, t0);
+  const unsigned long long t1 = PROF ? pf->now() : 0ull;
   // species rows of dw/dC (sparse, lane-owned rows of J)
   const bool isSp = lane >= 1 && lane <= K;
-  double* Jr = w.J + lane * S;
+  double* Jr = w.J + lane * S;  // S = NP + 1: every static column index stays in the row
   if (lane < N) {
 #pragma unroll
-    for (int j = 0; j < NP + 2; ++j)
-      if (j < S) Jr[j] = 0.0;
+    for (int j = 0; j < NP + 1; ++j) Jr[j] = 0.0;
   }
   wsync();
   double om = 0.0, dwdT = 0.0, adense = 0.0;
@@ -303,9 +353,9 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
       if (r >= m.d.R0) {
         const double dm = nu * w.rdm[r];
         adense += dm;
-        const TbEntry& te = m.tb[r - m.d.R0];
-#pragma unroll
-        for (int q = 0; q < MAXTB; ++q) atomicAdd(Jr + 1 + te.sp[q], dm * te.de[q]);
+        const int e1 = m.tbp[r - m.d.R0 + 1];
+#pragma clang loop unroll(disable)
+        for (int e = m.tbp[r - m.d.R0]; e < e1; ++e) atomicAdd(Jr + 1 + m.tbs[e], dm * m.tbd[e]);
       }
     }
   }
@@ -318,16 +368,13 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
     double sk = 0.0;
 #pragma unroll
     for (int j = 1; j < NP; ++j) {
-      if (j < N) {
-        const double v = Jr[j] + adense;
-        row[j] = v;
-        sk += w.C[j - 1] * v;
-      }
+      const double v = j < N ? Jr[j] + adense : 0.0;
+      row[j] = v;
+      sk += (j < N ? w.C[j - 1] : 0.0) * v;
     }
     const double gam = Wk * x.Wbar * x.iRho * (om - sk);
 #pragma unroll
-    for (int j = 1; j < NP; ++j)
-      if (j < N) Jr[j] = m.iW[j - 1] * (Wk * row[j] + gam);
+    for (int j = 1; j < NP; ++j) Jr[j] = j < N ? m.iW[j - 1] * (Wk * row[j] + gam) : 0.0;
     Jr[0] = Wk * x.iRho * (dwdT - sk * x.iT + om * x.iT);
     fk = Wk * om * x.iRho;
     // mass-specific enthalpy for the T row (g/RT is no longer needed)
@@ -342,12 +389,33 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
   // T row: column sums of the species rows weighted by mass enthalpy
   if (lane < N) {
     double acc = 0.0;
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int k = 0;
 #pragma clang loop unroll(disable)
-    for (int k = 0; k < K; ++k) acc += w.g[k] * w.J[(1 + k) * S + lane];
+    for (; k + 4 <= K; k += 4) {
+      acc += w.g[k] * w.J[(1 + k) * S + lane];
+      a1 += w.g[k + 1] * w.J[(2 + k) * S + lane];
+      a2 += w.g[k + 2] * w.J[(3 + k) * S + lane];
+      a3 += w.g[k + 3] * w.J[(4 + k) * S + lane];
+    }
+#pragma clang loop unroll(disable)
+    for (; k < K; ++k) acc += w.g[k] * w.J[(1 + k) * S + lane];
+    acc = (acc + a1) + (a2 + a3);
     w.J[lane] = (lane == 0) ? -(acc + s1 + fT * dcpdT) / x.cp : -(acc + fT * cpm) / x.cp;
   }
   wsync();
+  if (PROF) pf->add(7, t1);
   return lane == 0 ? fT : fk;
+}
+
+// 1/x from the hardware estimate refined by two Newton steps (within an ulp
+// or two of the correctly rounded quotient for normal x).
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
 }
 
 // LU with partial pivoting of the row-per-lane matrix.  No rows move: the
@@ -358,8 +426,8 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
 // Inside a phase the four columns of chunk P rotate through c0..c3 so that
 // the pivot column is always c0; every register index is static.
 // Returns the 1-based step of a zero pivot, or 0.
-template <int NP>
-__device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep, double& myrdiag) {
+template <int NP, bool BCAST_LDS = CHEM_LU_BCAST_LDS>
+__device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep, double& myrdiag, double* bc) {
   mystep = lane < N ? -1 : (1 << 20);
   myrdiag = 0.0;
   int info = 0;
@@ -381,7 +449,7 @@ __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep,
       if (sing && info == 0) info = k + 1;
       const int p = sing ? 0 : uniform_int(__builtin_ctzll(ballot(elig && key == kmax)));
       const double piv = readlane(c0, p);
-      const double rp = 1.0 / piv;
+      const double rp = recip(piv);
       const bool upd = elig && lane != p && !sing;
       if (lane == p && !sing) {
         mystep = k;
@@ -389,7 +457,25 @@ __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep,
       }
       const double l = upd ? c0 * rp : 0.0;
       // c1..c3 hold columns k+1.. of the chunk first, then finished columns
-      double u1 = readlane(c1, p), u2 = readlane(c2, p), u3 = readlane(c3, p);
+      double u1, u2, u3;
+      if (BCAST_LDS) {
+        // the pivot lane publishes its row in LDS, every lane reads it back
+        if (lane == p) {
+          bc[1] = c1;
+          bc[2] = c2;
+          bc[3] = c3;
+#pragma unroll
+          for (int j = k0 + 4; j < NP; ++j) bc[j - k0] = row[j];
+        }
+        wsync();
+        u1 = bc[1];
+        u2 = bc[2];
+        u3 = bc[3];
+      } else {
+        u1 = readlane(c1, p);
+        u2 = readlane(c2, p);
+        u3 = readlane(c3, p);
+      }
       u1 = kk <= 2 ? u1 : 0.0;
       u2 = kk <= 1 ? u2 : 0.0;
       u3 = kk == 0 ? u3 : 0.0;
@@ -398,7 +484,8 @@ __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep,
       c3 = fma(-l, u3, c3);
       c0 = upd ? l : c0;
 #pragma unroll
-      for (int j = k0 + 4; j < NP; ++j) row[j] = fma(-l, readlane(row[j], p), row[j]);
+      for (int j = k0 + 4; j < NP; ++j) row[j] = fma(-l, BCAST_LDS ? bc[j - k0] : readlane(row[j], p), row[j]);
+      if (BCAST_LDS) wsync();
       const double t = c0;
       c0 = c1;
       c1 = c2;
@@ -422,28 +509,43 @@ __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep,
   return info;
 }
 
-// Solve M x = b with the factors of lu_factor; lane i holds b_i and gets x_i.
+// Moves the factored rows into pivot order (lane k receives the row chosen
+// at step k), so that L is unit lower and U upper with lane = row; src is the
+// lane each lane took its row from.
 template <int NP>
-__device__ inline double lu_solve(const double (&row)[NP], int N, int lane, int mystep, double myrdiag, double b) {
+__device__ inline int permute_rows(double (&row)[NP], int N, int lane, int mystep, double& myrdiag, int* slot) {
+  if (lane < N) slot[mystep] = lane;
+  wsync();
+  const int src = lane < N ? slot[lane] : lane;
+  wsync();
+#pragma unroll
+  for (int j = 0; j < NP; ++j) row[j] = __shfl(row[j], src);
+  myrdiag = __shfl(myrdiag, src);
+  return src;
+}
+
+// Solve M x = b with the permuted factors; lane i holds b_i and gets x_i.
+// The right-hand side is gathered into pivot order, then forward substitution
+// with the unit-lower L and back substitution with U (both by columns, the
+// value of step k broadcast from lane k).
+template <int NP>
+__device__ inline double lu_solve(const double (&row)[NP], int N, int lane, int src, double myrdiag, double b) {
+  // padding lanes carry b = 0 and zero rows, so all NP steps run unconditionally
+  (void)N;
+  b = __shfl(b, src);
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
-    if (k < N) {
-      const int p = uniform_int(__builtin_ctzll(ballot(mystep == k)));
-      const double yk = readlane(b, p);
-      if (mystep > k) b = fma(-row[k], yk, b);
-    }
+    const double yk = readlane(b, k);
+    const double v = fma(-row[k], yk, b);
+    b = lane > k ? v : b;
   }
-  double x = 0.0;
 #pragma unroll
   for (int k = NP - 1; k >= 0; --k) {
-    if (k < N) {
-      const int p = uniform_int(__builtin_ctzll(ballot(mystep == k)));
-      const double xk = readlane(b * myrdiag, p);
-      if (mystep < k) b = fma(-row[k], xk, b);
-      if (lane == k) x = xk;
-    }
+    const double xk = readlane(b * myrdiag, k);
+    const double v = fma(-row[k], xk, b);
+    b = lane < k ? v : b;
   }
-  return x;
+  return b * myrdiag;
 }
 
 // M = I/(gamma h) - J from the LDS Jacobian into row registers.  Returns
@@ -460,7 +562,7 @@ __device__ inline bool form_matrix(const CellWs& w, int N, int S, int lane, doub
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-      if (j < N) row[j] = -Jr[j];
+      row[j] = j < N ? -Jr[j] : 0.0;
       chk += row[j];
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -473,13 +575,22 @@ __device__ inline bool form_matrix(const CellWs& w, int N, int S, int lane, doub
 // and err (lane-local); returns 1 if M is singular and 2 if M holds a
 // non-finite value.  Stage vectors live in a shift register: after stage i,
 // K0 = K_i, K1 = K_{i-1}, ..., so coefficient a_ij multiplies K_{i-1-j}.
-template <int NP>
+template <int NP, bool PROF>
 __device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosTable& tab, double p, int lane,
                                   double y, double f0, double h, double (&row)[NP], double& ynew, double& err,
-                                  int& mystep, double& myrdiag) {
+                                  int& mystep, double& myrdiag, Prof<PROF>& pf) {
   const int N = m.d.N;
-  if (!form_matrix<NP>(w, N, m.d.S, lane, 1.0 / (tab.gamma * h), row)) return 2;
-  if (lu_factor<NP>(row, N, lane, mystep, myrdiag)) return 1;
+  pf.start();
+  const bool okm = form_matrix<NP>(w, N, m.d.S, lane, 1.0 / (tab.gamma * h), row);
+  pf.stop(1);
+  if (!okm) return 2;
+  const int info = lu_factor<NP>(row, N, lane, mystep, myrdiag, w.bc);
+  if (info) {
+    pf.stop(2);
+    return 1;
+  }
+  const int src = permute_rows<NP>(row, N, lane, mystep, myrdiag, w.slot);
+  pf.stop(2);
   const double ih = 1.0 / h;
   const int s = tab.s;
   double K0 = 0.0, K1 = 0.0, K2 = 0.0, K3 = 0.0;
@@ -492,10 +603,14 @@ __device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosT
     const double a2 = i >= 3 ? tab.a[i][i - 3] : 0.0, c2 = i >= 3 ? tab.c[i][i - 3] : 0.0;
     if (i > 0 && tab.newf[i]) {
       const double Yi = y + a0 * K0 + a1 * K1 + a2 * K2;
+      pf.start();
       fi = rhs(m, w, lane < N ? Yi : 0.0, p, lane);
+      pf.stop(3);
     }
     const double r = fi + ih * (c0 * K0 + c1 * K1 + c2 * K2);
-    const double ki = lu_solve<NP>(row, N, lane, mystep, myrdiag, lane < N ? r : 0.0);
+    pf.start();
+    const double ki = lu_solve<NP>(row, N, lane, src, myrdiag, lane < N ? r : 0.0);
+    pf.stop(4);
     K3 = K2;
     K2 = K1;
     K1 = K0;
@@ -515,9 +630,11 @@ __device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosT
 // follows the constants in a.ctl (accept iff err <= 1, no growth right after a
 // rejection, non-finite err rejects with fac_min, the last step is clipped to
 // dt and h_out is the last unclipped proposal capped at dt).
-template <int NP>
+template <int NP, bool PROF>
 __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs& a, int64_t c) {
   const int lane = lane_id();
+  Prof<PROF> pf;
+  const unsigned long long t_begin = PROF ? __builtin_readcyclecounter() : 0ull;
   const int N = m.d.N;
   if (lane == 0) {  // padding species: C = 1, g/RT = h/RT = 0
     w.C[m.d.K] = 1.0;
@@ -539,7 +656,9 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
   double myrdiag;
   int ntape = 0;
   while (status == ST_OK && t < dt) {
-    const double f0 = jac_pass<NP>(m, w, y, a.p, lane, row);
+    pf.start();
+    const double f0 = jac_pass<NP, PROF>(m, w, y, a.p, lane, row, &pf);
+    pf.stop(0);
     bool fresh = true;
     int nsing = 0;
     bool accepted = false;
@@ -552,7 +671,8 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
       ++attempts;
       if (fresh && ballot(lane < N && !__builtin_isfinite(f0))) { status = ST_NONFINITE; break; }
       double ynew, err;
-      const int rc = ros_attempt<NP>(m, w, kTables[a.method], a.p, lane, y, f0, h, row, ynew, err, mystep, myrdiag);
+      const int rc =
+          ros_attempt<NP, PROF>(m, w, kTables[a.method], a.p, lane, y, f0, h, row, ynew, err, mystep, myrdiag, pf);
       if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
       fresh = false;
       if (rc) {
@@ -608,6 +728,14 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
     if (a.steps) a.steps[c] = steps;
     if (a.rejects) a.rejects[c] = rejects;
     if (a.status) a.status[c] = status;
+  }
+  if (PROF && lane < 8) {
+    unsigned long long v = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (lane == i) v = pf.c[i];
+    if (lane == 5) v = __builtin_readcyclecounter() - t_begin;
+    a.prof[c * 8 + lane] = v;
   }
 }
 

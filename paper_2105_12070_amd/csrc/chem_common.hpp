@@ -24,15 +24,12 @@ struct MechDims {
   int L;           // species->reaction incidence entries
   // byte offsets inside the LDS-staged blob
   int o_lnA, o_b, o_th, o_sp, o_W, o_iW, o_cptr, o_cent;
+  int o_tbp, o_tbs, o_tbd, o_troe;  // third-body lists and Troe data
   int lds_bytes;   // size of the staged blob (multiple of 16)
 };
 
-// Per third-body / Troe reaction: up to MAXTB (species, eff - 1) pairs.
-struct TbEntry {
-  uint8_t sp[MAXTB];
-  double de[MAXTB];
-};
-
+// Third-body / Troe reaction r >= R0 has the non-unit efficiencies
+// tbs[e], 1 + tbd[e] for e in [tbp[r-R0], tbp[r-R0+1]) (at most MAXTB).
 // Troe data per falloff reaction: alpha, 1/T***, 1/T*, T**, lnA0, b0, theta0, 0.
 constexpr int TROE_STRIDE = 8;
 
@@ -72,8 +69,6 @@ struct Controller {
 struct IntArgs {
   const uint8_t* blob;      // LDS-staged part of the mechanism (global copy)
   const double* nasa;       // [K][16] Tmid, lo a1..a7, hi a1..a7, pad
-  const TbEntry* tb;        // [R - R0]
-  const double* troe;       // [R - R1][8]
   MechDims d;
   int method;               // index into kTables
   double q;                 // controller exponent 1/q (4 ROS4, 3 Rodas3)
@@ -93,6 +88,7 @@ struct IntArgs {
   double* tape_h;           // [ncells][max_tape]
   double* tape_y;           // [ncells][max_tape/ckpt + 1][N]
   int max_tape, ckpt;
+  unsigned long long* prof; // [ncells][8] per-phase cycle counts, or NULL
 };
 
 // ------------------------------------------------------------ wave primitives
