@@ -60,6 +60,21 @@ def flop_model(mech: dict, method_stages: int = 4, new_f: int = 2) -> dict:
     return dict(f_rhs=f_rhs, f_lu=f_lu, f_solve=f_solve, f_att=f_att, f_step=f_jac, L=L)
 
 
+def adjoint_flop_model(mech: dict, method_stages: int = 4, new_f: int = 3) -> dict:
+    """Algorithmic FP64 operations of one reverse step (estimates, transcendentals count 1).
+
+    Each accepted step is replayed twice (segment replay and reverse replay:
+    Jacobian pass + one attempt each).  The reverse step takes s transposed
+    solves, s dual-number vector-Jacobian products of f (the second-order
+    terms, costed as 3 first-order ones) and one first-order product per new f
+    evaluation (stage sources); a first-order product of f costs ~3 f.
+    """
+    fm = flop_model(mech)
+    f_vjp = 3 * fm["f_rhs"]
+    f_rev = method_stages * (fm["f_solve"] + 3 * f_vjp) + new_f * f_vjp
+    return dict(f_replay=2 * (fm["f_step"] + fm["f_att"]), f_rev=f_rev, **fm)
+
+
 def cpu_baseline(w, mech, st0, target_s=12.0):
     import oracle
     oracle.build(force=False)
@@ -88,6 +103,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--graph", action="store_true", help="launch through the cached hipGraph")
     ap.add_argument("--cells", type=int, default=0, help="integrate only the first CELLS cells (profiling)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time chem_integrate_adjoint (gradients of sum_cells[T + w.Y] w.r.t. lnA, b, theta)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the cells are independent, and the multi-GPU "
@@ -97,6 +114,8 @@ def main():
     import torch
     from paper_2105_12070_amd import chem
 
+    if args.adjoint:
+        return bench_adjoint(args)
     w = WORKLOADS[args.config]
     mech = w.mechanism()
     st0_np = w.states(mech)
@@ -191,6 +210,104 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, mech, st0_np)
     print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    import torch
+    from paper_2105_12070_amd import chem
+    from paper_2105_12070_amd.inputs import objective_weights
+
+    name = args.config if args.config != "c2_54sp" else "c4_adj"
+    w = WORKLOADS[name]
+    mech = w.mechanism()
+    st0_np = w.states(mech)
+    if args.cells:
+        st0_np = np.ascontiguousarray(st0_np[:, :args.cells])
+    nc = st0_np.shape[1]
+    dev = torch.device("cuda:0")
+    m = chem.Mechanism(mech)
+    st0 = torch.tensor(st0_np, device=dev)
+    lam = torch.empty_like(st0)
+    lam[0] = 1.0
+    lam[1:] = torch.tensor(objective_weights(w.n_species), device=dev)[:, None]
+    h = torch.zeros(nc, dtype=torch.float64, device=dev)
+    ck, max_tape = 8, 8192
+    ev = None
+
+    def one_step(evp=None):
+        h.zero_()
+        if evp:
+            evp[0].record()
+        r = chem.integrate_adjoint(m, st0, h, w.p_pa, w.dt, w.rtol, w.atol, lam, checkpoint_every=ck,
+                                   max_tape=max_tape)
+        if evp:
+            evp[1].record()
+        return r
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        res = one_step(evs[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    call_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    out, lam0, grad, steps, status = res
+    st = status.cpu().numpy()
+    sp = steps.cpu().numpy().astype(np.int64)
+    if np.any(st != 0):
+        print(f"# warning: {np.sum(st != 0)} cells with nonzero status {np.bincount(st)}", file=sys.stderr)
+    # forward-only rate on the same cells and the plain one-cell-per-block launch, for context
+    s2 = st0.clone()
+    h.zero_()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    chem.integrate(m, s2, h, w.p_pa, w.dt, w.rtol, w.atol)
+    b.record()
+    s2.copy_(st0)
+    h.zero_()
+    c, d = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c.record()
+    chem.integrate(m, s2, h, w.p_pa, w.dt, w.rtol, w.atol, options=chem.Options(persistent=0, waves_per_block=1))
+    d.record()
+    torch.cuda.synchronize()
+    fwd_ms, plain_ms = a.elapsed_time(b), c.elapsed_time(d)
+    fm = adjoint_flop_model(mech)
+    flops_adj = float(np.sum(sp * (fm["f_replay"] + fm["f_rev"])))
+    adj_kernel_ms = max(call_ms - fwd_ms, 1e-6)
+    achieved = flops_adj / (adj_kernel_ms * 1e-3) / 1e12
+    value = nc * args.steps / elapsed
+    outd = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-gradients/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator: element-balanced Chemkin-form mechanism, random states)",
+        "config": {"workload": f"{w.name}: {w.n_species} species / {w.n_reactions} reactions, {nc} cells, "
+                               f"p = {w.p_pa:g} Pa, dt = {w.dt:g} s, rtol {w.rtol:g}, atol {w.atol:g}, ROS4; "
+                               f"gradient of sum_cells [T + w.Y](dt) w.r.t. lnA, b, theta of all "
+                               f"{w.n_reactions} reactions and the initial states; checkpoints every {ck} steps",
+                   "n_cells": nc, "N": w.N},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "kernel": "k_adjoint",
+                     "kernel_ms": adj_kernel_ms, "flops_per_launch": flops_adj,
+                     "note": "reverse-sweep FLOPs estimated by adjoint_flop_model; kernel time = call time "
+                             "minus the forward integration time"},
+        "forward_cells_per_s": nc / (fwd_ms * 1e-3),
+        "plain_one_cell_per_block_cells_per_s": nc / (plain_ms * 1e-3),
+        "adjoint_over_forward_time": call_ms / fwd_ms,
+        "steps_mean": float(sp.mean()),
+    }
+    print(json.dumps(outd), flush=True)
 
 
 if __name__ == "__main__":

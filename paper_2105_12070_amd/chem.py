@@ -177,6 +177,47 @@ def integrate_adjoint(mech: Mechanism, state0, h, p, dt, rtol, atol, lambda_fina
     return out, lam0, grad, steps, status
 
 
+class IntegrateFn(torch.autograd.Function):
+    """state_final = integrate(state0; lnA, b, theta) with a discrete-adjoint backward.
+
+    The forward pass is chem_integrate from a cold step size; the backward pass
+    calls chem_integrate_adjoint, which recomputes the forward pass with its
+    tape (identical arithmetic, so the same accepted steps) and sweeps it
+    backwards.  Gradients flow to state0 and to the three Arrhenius arrays
+    (device tensors of length R in descriptor order, loaded into the
+    mechanism on every call).
+    """
+
+    @staticmethod
+    def forward(ctx, state0, lnA, b, theta, mech, p, dt, rtol, atol, options, checkpoint_every):
+        mech.set_arrhenius(lnA.detach().contiguous(), b.detach().contiguous(), theta.detach().contiguous())
+        st = state0.detach().clone().contiguous()
+        h = torch.zeros(st.shape[1], dtype=torch.float64, device=st.device)
+        status = torch.empty(st.shape[1], dtype=torch.int32, device=st.device)
+        integrate(mech, st, h, p, dt, rtol, atol, options=options, status=status)
+        ctx.save_for_backward(state0.detach(), lnA.detach(), b.detach(), theta.detach())
+        ctx.cfg = (mech, p, dt, rtol, atol, options, checkpoint_every)
+        ctx.status = status
+        return st
+
+    @staticmethod
+    def backward(ctx, gout):
+        state0, lnA, b, theta = ctx.saved_tensors
+        mech, p, dt, rtol, atol, options, ck = ctx.cfg
+        mech.set_arrhenius(lnA.contiguous(), b.contiguous(), theta.contiguous())
+        h = torch.zeros(state0.shape[1], dtype=torch.float64, device=state0.device)
+        _, lam0, grad, _, status = integrate_adjoint(mech, state0.contiguous(), h, p, dt, rtol, atol,
+                                                     gout.contiguous(), options=options, checkpoint_every=ck)
+        ctx.adjoint_status = status
+        return lam0, grad[0], grad[1], grad[2], None, None, None, None, None, None, None
+
+
+def integrate_diff(mech: Mechanism, state0, lnA, b, theta, p, dt, rtol=1e-6, atol=1e-10,
+                   options: Options | None = None, checkpoint_every=8):
+    """Differentiable integration over one CFD step (see IntegrateFn)."""
+    return IntegrateFn.apply(state0, lnA, b, theta, mech, p, dt, rtol, atol, options, checkpoint_every)
+
+
 def rhs(mech: Mechanism, state, p):
     _dev(state, torch.float64, "state")
     N, ld = state.shape

@@ -169,9 +169,13 @@ struct chem_mech {
   hipGraph_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
   GraphKey gkey;
-  // adjoint workspace
+  // adjoint workspace and incidence lists
   void* adj_ws = nullptr;
   size_t adj_ws_bytes = 0;
+  int32_t* adj_sptr = nullptr;
+  uint32_t* adj_sent = nullptr;
+  int32_t* adj_tptr = nullptr;
+  uint32_t* adj_tent = nullptr;
 };
 
 namespace {
@@ -422,6 +426,28 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   std::vector<double> nasa((size_t)16 * K, 0.0);
   for (int k = 0; k < K; ++k)
     for (int i = 0; i < 15; ++i) nasa[16 * k + i] = desc->nasa7[15 * k + i];
+  // adjoint incidence: species -> (reaction, molecule slot) and -> (reaction, efficiency entry)
+  std::vector<std::vector<uint32_t>> sinc(K), tinc(K);
+  for (int ri = 0; ri < R; ++ri)
+    for (int sl = 0; sl < 6; ++sl) {
+      const int spc = (int)((sp[ri] >> (8 * sl)) & 0xFF);
+      if (spc < K) sinc[spc].push_back(((uint32_t)ri << 3) | (uint32_t)sl);
+    }
+  if (tbs.size() >= 4096 || R >= (1 << 20)) return fail(CHEM_EUNSUPPORTED, "mechanism too large for the adjoint tables");
+  for (int ri = R0; ri < R; ++ri)
+    for (int e = tbp[ri - R0]; e < tbp[ri - R0 + 1]; ++e) tinc[tbs[e]].push_back(((uint32_t)ri << 12) | (uint32_t)e);
+  std::vector<int32_t> sptr(K + 1, 0), tptr(K + 1, 0);
+  std::vector<uint32_t> sent, tent;
+  for (int k = 0; k < K; ++k) {
+    sptr[k] = (int32_t)sent.size();
+    sent.insert(sent.end(), sinc[k].begin(), sinc[k].end());
+    tptr[k] = (int32_t)tent.size();
+    tent.insert(tent.end(), tinc[k].begin(), tinc[k].end());
+  }
+  sptr[K] = (int32_t)sent.size();
+  tptr[K] = (int32_t)tent.size();
+  if (sent.empty()) sent.push_back(0);
+  if (tent.empty()) tent.push_back(0);
   chem_mech* m = new chem_mech();
   m->d = d;
   m->h_perm.assign(order.begin(), order.end());
@@ -435,8 +461,15 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   if (m->max_lds < d.lds_bytes + (int)cell_bytes(d))
     return cleanup(CHEM_EUNSUPPORTED, "mechanism workspace needs more LDS than one workgroup has");
   if (hipMalloc(&m->blob, blob.size()) != hipSuccess || hipMalloc(&m->nasa, 8 * nasa.size()) != hipSuccess ||
-      hipMalloc(&m->perm, 4 * (size_t)std::max(R, 1)) != hipSuccess || hipMalloc(&m->queue, 64) != hipSuccess)
+      hipMalloc(&m->perm, 4 * (size_t)std::max(R, 1)) != hipSuccess || hipMalloc(&m->queue, 64) != hipSuccess ||
+      hipMalloc(&m->adj_sptr, 4 * sptr.size()) != hipSuccess || hipMalloc(&m->adj_sent, 4 * sent.size()) != hipSuccess ||
+      hipMalloc(&m->adj_tptr, 4 * tptr.size()) != hipSuccess || hipMalloc(&m->adj_tent, 4 * tent.size()) != hipSuccess)
     return cleanup(CHEM_ENOMEM, "device allocation failed");
+  if (hipMemcpy(m->adj_sptr, sptr.data(), 4 * sptr.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->adj_sent, sent.data(), 4 * sent.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->adj_tptr, tptr.data(), 4 * tptr.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->adj_tent, tent.data(), 4 * tent.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return cleanup(CHEM_EHIP, "upload failed");
   if (hipMemcpy(m->blob, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->nasa, nasa.data(), 8 * nasa.size(), hipMemcpyHostToDevice) != hipSuccess ||
       (R > 0 && hipMemcpy(m->perm, order.data(), 4 * (size_t)R, hipMemcpyHostToDevice) != hipSuccess))
@@ -455,6 +488,10 @@ void chem_free_mechanism(chem_mech* m) {
   hipFree(m->perm);
   hipFree(m->queue);
   hipFree(m->adj_ws);
+  hipFree(m->adj_sptr);
+  hipFree(m->adj_sent);
+  hipFree(m->adj_tptr);
+  hipFree(m->adj_tent);
   delete m;
 }
 

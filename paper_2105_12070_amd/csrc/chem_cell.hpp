@@ -578,7 +578,8 @@ __device__ inline bool form_matrix(const CellWs& w, int N, int S, int lane, doub
 template <int NP, bool PROF>
 __device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosTable& tab, double p, int lane,
                                   double y, double f0, double h, double (&row)[NP], double& ynew, double& err,
-                                  int& mystep, double& myrdiag, Prof<PROF>& pf) {
+                                  int& mystep, double& myrdiag, Prof<PROF>& pf, double* kst = nullptr,
+                                  int* srcout = nullptr) {
   const int N = m.d.N;
   pf.start();
   const bool okm = form_matrix<NP>(w, N, m.d.S, lane, 1.0 / (tab.gamma * h), row);
@@ -616,6 +617,13 @@ __device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosT
     K1 = K0;
     K0 = ki;
   }
+  if (kst) {  // stage order: kst[i] = K_i (four-stage tables)
+    kst[0] = K3;
+    kst[1] = K2;
+    kst[2] = K1;
+    kst[3] = K0;
+    *srcout = src;
+  }
   // after s stages K0 = K_{s-1}, K1 = K_{s-2}, ...
   const double m0 = tab.m[s - 1], e0 = tab.e[s - 1];
   const double m1 = s >= 2 ? tab.m[s - 2] : 0.0, e1 = s >= 2 ? tab.e[s - 2] : 0.0;
@@ -651,6 +659,8 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
   if (ballot(bad)) status = ST_NONFINITE;
   double t = 0.0;
   bool rej_last = false;
+  const int nck = a.tape_y ? a.max_tape / a.ckpt + 1 : 0;
+  if (a.tape_y && lane < N) a.tape_y[(c * (int64_t)nck) * N + lane] = y;
   double row[NP];
   int mystep;
   double myrdiag;
@@ -713,7 +723,7 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
         hprop = hn;
         rej_last = false;
         if (a.tape_y && ntape <= a.max_tape && (ntape % a.ckpt) == 0 && lane < N)
-          a.tape_y[(c * (int64_t)(a.max_tape / a.ckpt + 1) + ntape / a.ckpt) * N + lane] = y;
+          a.tape_y[(c * (int64_t)nck + ntape / a.ckpt) * N + lane] = y;
       } else {
         ++rejects;
         hprop = h * fac;

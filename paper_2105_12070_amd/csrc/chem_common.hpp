@@ -39,6 +39,7 @@ constexpr int TROE_STRIDE = 8;
 struct RosTable {
   int s;
   int newf[4];      // stage i evaluates f at a point no earlier stage used
+  int src[4];       // the stage whose f evaluation stage i uses
   double gamma;
   double a[4][4], c[4][4], m[4], e[4];
 };
@@ -47,14 +48,14 @@ struct RosTable {
 // order 4 with an embedded order-3 estimate; 1: Rodas3 (Sandu et al. 1997),
 // stiffly accurate, order 3(2).
 __constant__ const RosTable kTables[2] = {
-    {4, {0, 1, 1, 0}, 0.57282,
+    {4, {0, 1, 1, 0}, {0, 1, 2, 2}, 0.57282,
      {{0, 0, 0, 0}, {2.0, 0, 0, 0}, {1.867943637803922, 0.2344449711399156, 0, 0},
       {1.867943637803922, 0.2344449711399156, 0.0, 0}},
      {{0, 0, 0, 0}, {-7.137615036412310, 0, 0, 0}, {2.580708087951457, 0.6515950076447975, 0, 0},
       {-2.137148994382534, -0.3214669691237626, -0.6949742501781779, 0}},
      {2.255570073418735, 0.2870493262186792, 0.4353179431840180, 1.093502252409163},
      {-0.2815431932141155, -0.07276199124938920, -0.1082196201495311, -1.093502252409163}},
-    {4, {0, 0, 1, 1}, 0.5,
+    {4, {0, 0, 1, 1}, {0, 0, 2, 3}, 0.5,
      {{0, 0, 0, 0}, {0, 0, 0, 0}, {2.0, 0, 0, 0}, {2.0, 0, 1.0, 0}},
      {{0, 0, 0, 0}, {4.0, 0, 0, 0}, {1.0, -1.0, 0, 0}, {1.0, -1.0, -8.0 / 3.0, 0}},
      {2.0, 0.0, 1.0, 1.0},

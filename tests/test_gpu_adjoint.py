@@ -1,0 +1,310 @@
+"""Parity of the discrete adjoint (chem_integrate_adjoint, through the C ABI)
+with the oracle's tangent-linear model.
+
+The adjoint differentiates the Rosenbrock map with the accepted step sizes
+frozen.  The oracle records its own accepted steps for each cell and runs its
+forward-sensitivity (tangent-linear) replay along chosen directions, so the
+identity  lambda_final . dy(dt) = lambda0 . dy0 + grad . dparams  holds between
+the two for every direction, up to rounding and to the difference between the
+two step sequences.  Only cells whose GPU step count equals the oracle's carry
+a nonzero lambda_final (a cell with zero lambda contributes exactly zero).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2105_12070_amd.inputs import WORKLOADS, objective_weights  # noqa: E402
+
+sys.path.insert(0, __file__.rsplit("/", 1)[0])
+from mechs import isomer_mech  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def chem():
+    from paper_2105_12070_amd import chem as c
+    assert torch.cuda.is_available()
+    return c
+
+
+DEV = "cuda:0"
+
+
+def gpu_adjoint(chem, mech, st0, p, dt, rtol, atol, lam, ck=8, max_tape=0, method=0):
+    m = chem.Mechanism(mech)
+    s0 = torch.tensor(st0, device=DEV)
+    h = torch.zeros(st0.shape[1], dtype=torch.float64, device=DEV)
+    lt = torch.tensor(lam, device=DEV)
+    opt = chem.Options(method=method)
+    out, lam0, grad, steps, status = chem.integrate_adjoint(m, s0, h, p, dt, rtol, atol, lt, options=opt,
+                                                            checkpoint_every=ck, max_tape=max_tape)
+    torch.cuda.synchronize()
+    return (out.cpu().numpy(), lam0.cpu().numpy(), grad.cpu().numpy(), steps.cpu().numpy(),
+            status.cpu().numpy())
+
+
+def gpu_steps(chem, mech, st0, p, dt, rtol, atol):
+    m = chem.Mechanism(mech)
+    s = torch.tensor(st0, device=DEV)
+    h = torch.zeros(st0.shape[1], dtype=torch.float64, device=DEV)
+    steps = torch.zeros(st0.shape[1], dtype=torch.int32, device=DEV)
+    chem.integrate(m, s, h, p, dt, rtol, atol, steps=steps)
+    return steps.cpu().numpy()
+
+
+def objective_lambda(K, nc):
+    lam = np.zeros((K + 1, nc))
+    lam[0] = 1.0
+    lam[1:] = objective_weights(K)[:, None]
+    return lam
+
+
+def dot_product_check(chem, name, nc, dt, rtol, atol, ndir, tol, seed=7, max_tape=0):
+    w = WORKLOADS[name]
+    mech = w.mechanism()
+    st0 = np.ascontiguousarray(w.states(mech)[:, :nc])
+    K, R = mech["n_species"], mech["n_reactions"]
+    om = oracle.Mech(mech)
+    recs = [oracle.integrate_record(om, st0[:, c], None, w.p_pa, dt, rtol, atol) for c in range(nc)]
+    gs = gpu_steps(chem, mech, st0, w.p_pa, dt, rtol, atol)
+    same = np.array([len(r[2]) == gs[c] for c, r in enumerate(recs)])
+    say(f"{name}: {same.sum()}/{nc} cells with the oracle's step count; steps {gs.min()}..{gs.max()}")
+    assert same.sum() >= max(2, nc // 2)
+    lam = objective_lambda(K, nc) * same[None, :]
+    out, lam0, grad, steps, status = gpu_adjoint(chem, mech, st0, w.p_pa, dt, rtol, atol, lam, max_tape=max_tape)
+    assert np.all(status == 0) and np.array_equal(steps, gs)
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for d in range(ndir):
+        dy0 = rng.standard_normal(st0.shape) * np.abs(st0) * 1e-3
+        dp = [rng.standard_normal(R), rng.standard_normal(R), rng.standard_normal(R) * 100.0]
+        lhs, scale = 0.0, 0.0
+        for c in np.nonzero(same)[0]:
+            _, dyo = oracle.tlm(om, st0[:, c], recs[c][2], w.p_pa, dy0=dy0[:, c], dlnA=dp[0], db=dp[1],
+                                dtheta=dp[2])
+            lhs += lam[:, c] @ dyo
+            scale += np.abs(lam[:, c]) @ np.abs(dyo)
+        rhs_s = np.sum(lam0 * dy0) + sum(grad[i] @ dp[i] for i in range(3))
+        err = abs(rhs_s - lhs) / scale
+        worst = max(worst, err)
+        say(f"  dir {d}: oracle {lhs:.12e}  gpu {rhs_s:.12e}  rel {err:.2e}")
+    assert worst <= tol, worst
+    return worst
+
+
+def test_adjoint_dot_product_c4_short_tight(chem):
+    # rtol 1e-10 / atol 1e-14 resolves the fastest modes: ~2000-4000 steps in 2e-10 s
+    dot_product_check(chem, "c4_adj", 6, 2e-10, 1e-10, 1e-14, 2, 1e-9, max_tape=8192)
+
+
+def test_adjoint_dot_product_c1_tight(chem):
+    dot_product_check(chem, "c1_10sp", 32, 1e-7, 1e-10, 1e-14, 3, 1e-9, max_tape=16384)
+
+
+def test_adjoint_dot_product_c4_metric(chem):
+    dot_product_check(chem, "c4_adj", 12, WORKLOADS["c4_adj"].dt, 1e-6, 1e-10, 2, 1e-7)
+
+
+def test_adjoint_dot_product_c1_metric(chem):
+    dot_product_check(chem, "c1_10sp", 32, WORKLOADS["c1_10sp"].dt, 1e-6, 1e-10, 3, 1e-7)
+
+
+def test_adjoint_dot_product_rodas3(chem):
+    w = WORKLOADS["c1_10sp"]
+    mech = w.mechanism()
+    st0 = np.ascontiguousarray(w.states(mech)[:, :8])
+    om = oracle.Mech(mech)
+    K, R = mech["n_species"], mech["n_reactions"]
+    recs = [oracle.integrate_record(om, st0[:, c], None, w.p_pa, w.dt, 1e-8, 1e-12, method="rodas3")
+            for c in range(8)]
+    lam = objective_lambda(K, 8)
+    out, lam0, grad, steps, status = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, 1e-8, 1e-12, lam, method=1,
+                                                 max_tape=16384)
+    assert np.all(status == 0)
+    keep = np.array([len(r[2]) == steps[c] for c, r in enumerate(recs)])
+    assert keep.sum() >= 4
+    lam_k = lam * keep
+    _, lam0, grad, _, status = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, 1e-8, 1e-12, lam_k, method=1,
+                                           max_tape=16384)
+    assert np.all(status == 0)
+    rng = np.random.default_rng(3)
+    dy0 = rng.standard_normal(st0.shape) * np.abs(st0) * 1e-3
+    dp = [rng.standard_normal(R) for _ in range(3)]
+    lhs, scale = 0.0, 0.0
+    for c in np.nonzero(keep)[0]:
+        _, dyo = oracle.tlm(om, st0[:, c], recs[c][2], w.p_pa, dy0=dy0[:, c], dlnA=dp[0], db=dp[1],
+                            dtheta=dp[2], method="rodas3")
+        lhs += lam_k[:, c] @ dyo
+        scale += np.abs(lam_k[:, c]) @ np.abs(dyo)
+    got = np.sum(lam0 * dy0) + sum(grad[i] @ dp[i] for i in range(3))
+    say(f"rodas3: oracle {lhs:.12e} gpu {got:.12e} rel {abs(got - lhs) / scale:.2e}")
+    assert abs(got - lhs) <= 1e-8 * scale
+
+
+def test_adjoint_elements_c4(chem):
+    """Per-parameter and per-component entries of one cell's gradient against
+    the oracle's tangent-linear model along unit directions, and against
+    central differences (h = 1e-6) of the oracle's replay with the same steps."""
+    w = WORKLOADS["c4_adj"]
+    mech = w.mechanism()
+    K, R = mech["n_species"], mech["n_reactions"]
+    st0 = np.ascontiguousarray(w.states(mech)[:, :4])
+    om = oracle.Mech(mech)
+    rec = oracle.integrate_record(om, st0[:, 0], None, w.p_pa, w.dt, w.rtol, w.atol)
+    gs = gpu_steps(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol)
+    assert gs[0] == len(rec[2])
+    lam = objective_lambda(K, 4)
+    lam[:, 1:] = 0.0
+    _, lam0, grad, _, status = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, lam)
+    assert status[0] == 0
+    assert np.all(lam0[:, 1:] == 0.0)
+    gmax = np.abs(grad).max(axis=1)
+    picks = []
+    for comp in range(3):
+        order = np.argsort(-np.abs(grad[comp]))
+        picks += [(comp, int(r)) for r in order[:4]]
+        picks += [(comp, int(r)) for r in np.random.default_rng(comp).choice(R, 2, replace=False)]
+    hs = rec[2]
+    names = ("dlnA", "db", "dtheta")
+    for comp, r in picks:
+        e = np.zeros(R)
+        e[r] = 1.0
+        _, dyo = oracle.tlm(om, st0[:, 0], hs, w.p_pa, **{names[comp]: e})
+        ref = lam[:, 0] @ dyo
+        got = grad[comp, r]
+        say(f"  {names[comp]}[{r}]: oracle {ref:.10e} gpu {got:.10e}")
+        assert abs(got - ref) <= 1e-7 * abs(ref) + 1e-9 * gmax[comp]
+    # central differences of the replayed map, h = 1e-6 on ln A of the top reactions
+    for r in np.argsort(-np.abs(grad[0]))[:3]:
+        vals = []
+        for s in (1.0, -1.0):
+            lnA = mech["lnA"].copy()
+            lnA[r] += s * 1e-6
+            yo = oracle.replay(oracle.Mech(mech, lnA=lnA), st0[:, 0], hs, w.p_pa)
+            vals.append(lam[:, 0] @ yo)
+        fd = (vals[0] - vals[1]) / 2e-6
+        say(f"  FD dlnA[{r}]: {fd:.8e} adjoint {grad[0, r]:.8e}")
+        assert abs(fd - grad[0, r]) <= 1e-5 * abs(grad[0, r]) + 1e-7 * gmax[0]
+    # lambda0 entries: T and the three largest species entries
+    comps = [0] + [int(i) for i in np.argsort(-np.abs(lam0[1:, 0]))[:3] + 1]
+    for i in comps:
+        e = np.zeros(K + 1)
+        e[i] = 1.0
+        _, dyo = oracle.tlm(om, st0[:, 0], hs, w.p_pa, dy0=e)
+        ref = lam[:, 0] @ dyo
+        say(f"  lambda0[{i}]: oracle {ref:.10e} gpu {lam0[i, 0]:.10e}")
+        assert abs(lam0[i, 0] - ref) <= 1e-7 * abs(ref) + 1e-9 * np.abs(lam0[:, 0]).max()
+
+
+@pytest.mark.parametrize("kind", ["elementary", "thirdbody"])
+def test_adjoint_isomer_closed_form(chem, kind):
+    """A <=> B with identical thermo: T is constant and Y_A - Y_B decays as
+    exp(-2 k t), so Y_A(t) and its derivatives are known in closed form."""
+    mech = isomer_mech(kind)
+    p, T = 101325.0, 1200.0
+    YA, YB, YI = 0.6, 0.1, 0.3
+    st0 = np.array([[T], [YA], [YB], [YI]])
+    lam = np.array([[0.0], [1.0], [0.0], [0.0]])  # objective Y_A(dt)
+    R_u = oracle.gas_constant()  # erg/(mol K)
+    lnk = mech["lnA"][0] + mech["b"][0] * np.log(T) - mech["theta"][0] / T
+    k = np.exp(lnk)
+    if kind == "thirdbody":
+        k *= 10.0 * p / (R_u * T)  # [M] = p/(R T) in mol/cm^3 (p in dyn/cm^2)
+    dt = 0.75 / k  # 2 k dt = 1.5: well inside the transient
+    _, lam0, grad, steps, status = gpu_adjoint(chem, mech, st0, p, dt, 1e-12, 1e-16, lam)
+    assert status[0] == 0
+    E = np.exp(-2.0 * k * dt)
+    dYA_dlnk = 0.5 * (YA - YB) * E * (-2.0 * k * dt)
+    dlnk_dT = mech["b"][0] / T + mech["theta"][0] / T ** 2 - (1.0 / T if kind == "thirdbody" else 0.0)
+    ref_grad = np.array([dYA_dlnk, dYA_dlnk * np.log(T), -dYA_dlnk / T])
+    ref_lam0 = np.array([dYA_dlnk * dlnk_dT, 0.5 * (1 + E), 0.5 * (1 - E), 0.0])
+    say(f"{kind}: steps {steps[0]}, grad {grad[:, 0]} ref {ref_grad}; lam0 {lam0[:, 0]} ref {ref_lam0}")
+    np.testing.assert_allclose(grad[:, 0], ref_grad, rtol=1e-7)
+    np.testing.assert_allclose(lam0[:, 0], ref_lam0, rtol=1e-7, atol=1e-12)
+
+
+def test_adjoint_checkpoint_interval_invariance(chem):
+    """The reverse sweep replays from checkpoints; the result must not depend
+    on the interval (bitwise: every replay repeats the same arithmetic)."""
+    w = WORKLOADS["c1_10sp"]
+    mech = w.mechanism()
+    st0 = np.ascontiguousarray(w.states(mech)[:, :64])
+    lam = objective_lambda(mech["n_species"], 64)
+    ref = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, lam, ck=8)
+    assert np.all(ref[4] == 0)
+    for ck in (1, 3, 64):
+        got = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, lam, ck=ck, max_tape=ck * 2048)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b)
+
+
+def test_adjoint_forward_equals_integrate(chem):
+    """The forward half of the adjoint is the plain integrator, bit for bit."""
+    w = WORKLOADS["c4_adj"]
+    mech = w.mechanism()
+    st0 = np.ascontiguousarray(w.states(mech)[:, :128])
+    m = chem.Mechanism(mech)
+    s = torch.tensor(st0, device=DEV)
+    h = torch.zeros(128, dtype=torch.float64, device=DEV)
+    chem.integrate(m, s, h, w.p_pa, w.dt, w.rtol, w.atol)
+    out = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, objective_lambda(mech["n_species"], 128))[0]
+    assert np.array_equal(out, s.cpu().numpy())
+
+
+def test_adjoint_tape_full_status(chem):
+    w = WORKLOADS["c1_10sp"]
+    mech = w.mechanism()
+    st0 = np.ascontiguousarray(w.states(mech)[:, :16])
+    lam = objective_lambda(mech["n_species"], 16)
+    _, lam0, grad, steps, status = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, lam, ck=2,
+                                                max_tape=4)
+    full = steps > 4
+    assert np.all(status[full] == 5) and np.all(status[~full] == 0)
+    assert np.all(lam0[:, full] == lam[:, full])  # no sweep for cells without a complete tape
+
+
+def test_adjoint_bitwise_reproducible_and_autograd(chem):
+    w = WORKLOADS["c1_10sp"]
+    mech = w.mechanism()
+    st0 = np.ascontiguousarray(w.states(mech)[:, :256])
+    lam = objective_lambda(mech["n_species"], 256)
+    a = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, lam)
+    b = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, lam)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    # torch.autograd.Function front end: same numbers
+    m = chem.Mechanism(mech)
+    s0 = torch.tensor(st0, device=DEV, requires_grad=True)
+    prm = [torch.tensor(mech[k], device=DEV, requires_grad=True) for k in ("lnA", "b", "theta")]
+    out = chem.integrate_diff(m, s0, *prm, w.p_pa, w.dt, w.rtol, w.atol)
+    psi = (out * torch.tensor(lam, device=DEV)).sum()
+    psi.backward()
+    assert np.array_equal(out.detach().cpu().numpy(), a[0])
+    assert np.array_equal(s0.grad.cpu().numpy(), a[1])
+    for i in range(3):
+        assert np.array_equal(prm[i].grad.cpu().numpy(), a[2][i])
+
+
+def test_adjoint_empty_and_errors(chem):
+    w = WORKLOADS["c1_10sp"]
+    mech = w.mechanism()
+    m = chem.Mechanism(mech)
+    N = mech["n_species"] + 1
+    s0 = torch.zeros((N, 0), dtype=torch.float64, device=DEV)
+    h = torch.zeros(0, dtype=torch.float64, device=DEV)
+    out, lam0, grad, steps, status = chem.integrate_adjoint(m, s0, h, w.p_pa, w.dt, w.rtol, w.atol,
+                                                            torch.zeros_like(s0))
+    assert np.all(grad.cpu().numpy() == 0.0)
+    s1 = torch.tensor(w.states(mech)[:, :4], device=DEV)
+    with pytest.raises(chem.ChemError):
+        chem.integrate_adjoint(m, s1, torch.zeros(4, dtype=torch.float64, device=DEV), w.p_pa, w.dt, w.rtol,
+                               w.atol, torch.zeros_like(s1), checkpoint_every=3, max_tape=10)
