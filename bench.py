@@ -83,7 +83,7 @@ def cpu_baseline(w, mech, st0, target_s=12.0):
     t0 = time.perf_counter()
     oracle.integrate(mech, st0[:, :n], None, w.p_pa, w.dt, w.rtol, w.atol, nthreads=nthreads)
     t1 = time.perf_counter() - t0
-    n2 = int(min(max(n, n * (target_s - t1) / max(t1, 1e-3)), 4096, st0.shape[1]))
+    n2 = int(min(max(n, n * (target_s - t1) / max(t1, 1e-3)), 65536, st0.shape[1]))
     t0 = time.perf_counter()
     oracle.integrate(mech, st0[:, :n2], None, w.p_pa, w.dt, w.rtol, w.atol, nthreads=nthreads)
     t2 = time.perf_counter() - t0
@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--graph", action="store_true", help="launch through the cached hipGraph")
+    ap.add_argument("--cost-order", action="store_true",
+                    help="persistent queue ordered by the previous call's step counts")
     ap.add_argument("--cells", type=int, default=0, help="integrate only the first CELLS cells (profiling)")
     ap.add_argument("--adjoint", action="store_true",
                     help="time chem_integrate_adjoint (gradients of sum_cells[T + w.Y] w.r.t. lnA, b, theta)")
@@ -137,8 +139,8 @@ def main():
         variant, _ = chem.autotune(m, st0[:, :sub].contiguous(), torch.zeros(sub, dtype=torch.float64, device=dev),
                                    w.p_pa, w.dt, w.rtol, w.atol)
         print(f"# autotune on {sub} cells: {variant}", file=sys.stderr, flush=True)
-    opt = chem.Options(use_graph=1 if args.graph else 0)
-    if args.graph:
+    opt = chem.Options(use_graph=1 if args.graph else 0, cost_order=1 if args.cost_order else 0)
+    if args.graph or args.cost_order:
         opt.persistent = 1
 
     def one_step(ev=None):
@@ -200,11 +202,13 @@ def main():
         "config": {"workload": f"{w.name}: {w.n_species} species / {w.n_reactions} reactions "
                                f"({w.n_thirdbody} third-body, {w.n_troe} Troe), {nc} cells, p = {w.p_pa:g} Pa, "
                                f"dt = {w.dt:g} s, rtol {w.rtol:g}, atol {w.atol:g}, ROS4",
-                   "n_cells": nc, "N": w.N, "variant": variant, "graph": bool(args.graph)},
+                   "n_cells": nc, "N": w.N, "variant": variant, "graph": bool(args.graph),
+                   "cost_order": bool(args.cost_order)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "kernel_ms": kern_ms, "flops_per_launch": flops},
         "steps_mean": float(sp.mean()), "rejects_mean": float(rj.mean()),
+        "steps_percentiles_0_50_90_99_100": np.percentile(sp, [0, 50, 90, 99, 100]).tolist(),
         "plain_one_cell_per_block_cells_per_s": plain,
     }
     if not args.no_cpu_baseline:

@@ -77,7 +77,10 @@ typedef struct chem_options {
   int32_t persistent; /* -1 auto [-1], 0 one launch slot per cell, 1 persistent grid + work queue */
   int32_t waves_per_block; /* cells per workgroup, 0 = auto [0] */
   int32_t grid_mult;  /* persistent grid = CUs x grid_mult workgroups, 0 = auto [0] */
-  int32_t cost_order; /* 1: the queue hands out cells by descending previous step count [0] */
+  int32_t cost_order; /* 1: the persistent queue hands out cells by descending step count,
+                         read from steps[] on entry (the previous call's counts; any
+                         values are valid, they only set the order); ignored when steps
+                         is NULL or the launch is not persistent [0] */
   int32_t use_graph;  /* 1: launch the reset + integrate sequence as a cached hipGraph [0] */
   uint64_t* phase_cycles; /* NULL [NULL], or device [ncells][8] shader-clock cycles per cell:
                              Jacobian pass, forming M, LU, stage f, solves, total, and the

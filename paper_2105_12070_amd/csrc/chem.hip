@@ -125,6 +125,58 @@ __global__ void k_set_arrhenius(uint8_t* blob, MechDims d, const int32_t* perm, 
   ((double*)(blob + d.o_th))[r] = th[o];
 }
 
+// Cost ordering of the work queue: cells are bucketed by floor(log2(previous
+// step count + 1)) and the buckets are handed out largest first, so the
+// longest cells start early and the tail of the persistent launch stays short.
+// The order inside a bucket is arbitrary; results do not depend on it.
+constexpr int NBUCKET = 32;
+
+__device__ __forceinline__ int cost_bucket(int32_t s) {
+  const unsigned v = (unsigned)min(max(s, 0), (1 << 30)) + 1u;
+  return 31 - __clz(v);
+}
+
+__global__ void k_order_count(const int32_t* steps, int64_t n, int* cnt) {
+  __shared__ int loc[NBUCKET];
+  if (threadIdx.x < NBUCKET) loc[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomicAdd(&loc[cost_bucket(steps[i])], 1);
+  __syncthreads();
+  if (threadIdx.x < NBUCKET && loc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], loc[threadIdx.x]);
+}
+
+// cnt[0..31] counts (cleared by the previous use), cnt[32..63] bucket cursors
+__global__ void k_order_clear(int* cnt) {
+  if (threadIdx.x < 2 * NBUCKET) cnt[threadIdx.x] = 0;
+}
+
+__global__ void k_order_scan(int* cnt) {
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int b = NBUCKET - 1; b >= 0; --b) {
+      cnt[NBUCKET + b] = off;
+      off += cnt[b];
+    }
+  }
+}
+
+__global__ void k_order_scatter(const int32_t* steps, int64_t n, int* cnt, int32_t* order) {
+  __shared__ int loc[NBUCKET], base[NBUCKET];
+  if (threadIdx.x < NBUCKET) loc[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0, r = 0;
+  if (i < n) {
+    b = cost_bucket(steps[i]);
+    r = atomicAdd(&loc[b], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < NBUCKET && loc[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cnt[NBUCKET + threadIdx.x], loc[threadIdx.x]);
+  __syncthreads();
+  if (i < n) order[base[b] + r] = (int32_t)i;
+}
+
 }  // namespace
 
 // ================================================================ host side
@@ -162,6 +214,9 @@ struct chem_mech {
   int32_t* perm = nullptr;  // device: internal -> descriptor reaction index
   std::vector<int32_t> h_perm;
   int* queue = nullptr;     // device work cursor
+  int32_t* order = nullptr; // device cost order of the queue
+  int64_t order_cap = 0;
+  int* order_cnt = nullptr; // device bucket counters [64]
   Variant tuned;
   bool has_tuned = false;
   // cached graph of the persistent launch
@@ -252,6 +307,17 @@ int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStrea
     }
     return 0;
   });
+}
+
+// Launches the cost ordering of ncells cells from steps into m->order.
+int launch_order(chem_mech* m, const int32_t* steps, int64_t ncells, hipStream_t s) {
+  const int nb = (int)((ncells + 255) / 256);
+  hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(64), 0, s, m->order_cnt);
+  hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(256), 0, s, steps, ncells, m->order_cnt);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, m->order_cnt);
+  hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, s, steps, ncells, m->order_cnt, m->order);
+  HIPCHK(hipGetLastError());
+  return 0;
 }
 
 bool finite_all(const double* p, size_t n) {
@@ -488,6 +554,8 @@ void chem_free_mechanism(chem_mech* m) {
   hipFree(m->perm);
   hipFree(m->queue);
   hipFree(m->adj_ws);
+  hipFree(m->order);
+  hipFree(m->order_cnt);
   hipFree(m->adj_sptr);
   hipFree(m->adj_sent);
   hipFree(m->adj_tptr);
@@ -572,10 +640,32 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
   a.prof = opt ? (unsigned long long*)opt->phase_cycles : nullptr;
   const Variant v = pick_variant(m, opt, ncells);
   hipStream_t s = (hipStream_t)stream;
+  const bool ordered = opt && opt->cost_order && steps && v.persistent;
+  if (ordered && m->order_cap < ncells) {
+    hipFree(m->order);
+    m->order = nullptr;
+    m->order_cap = 0;
+    if (hipMalloc(&m->order, sizeof(int32_t) * ncells) != hipSuccess)
+      return fail(CHEM_ENOMEM, "cost-order buffer allocation failed");
+    m->order_cap = ncells;
+  }
+  if (ordered && !m->order_cnt) {
+    if (hipMalloc(&m->order_cnt, sizeof(int) * 2 * NBUCKET) != hipSuccess)
+      return fail(CHEM_ENOMEM, "cost-order counter allocation failed");
+  }
+  if (ordered) a.order = m->order;
+  auto launch_all = [&](hipStream_t st) -> int {
+    if (ordered) {
+      const int rc = launch_order(m, steps, ncells, st);
+      if (rc) return rc;
+    }
+    return launch_integrate(m, a, v, st);
+  };
   if (opt && opt->use_graph && v.persistent) {
     GraphKey key;
     key.v = {(uintptr_t)state, (uintptr_t)h, (uintptr_t)ncells, (uintptr_t)ld, (uintptr_t)steps,
-             (uintptr_t)rejects, (uintptr_t)status, (uintptr_t)s, (uintptr_t)v.wpb, (uintptr_t)v.grid_mult};
+             (uintptr_t)rejects, (uintptr_t)status, (uintptr_t)s, (uintptr_t)v.wpb, (uintptr_t)v.grid_mult,
+             (uintptr_t)ordered, (uintptr_t)m->order};
     double dv[5] = {p, dt, rtol, atol, (double)(opt ? opt->method : 0)};
     for (double x : dv) {
       uint64_t u;
@@ -589,7 +679,7 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
       // be captured), launch the instantiated graph on the caller's stream
       if (!m->cap_stream) HIPCHK(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
       HIPCHK(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
-      int rc = launch_integrate(m, a, v, m->cap_stream);
+      int rc = launch_all(m->cap_stream);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(m->cap_stream, &g);
       if (rc) return rc;
@@ -601,7 +691,7 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
     HIPCHK(hipGraphLaunch(m->gexec, s));
     return CHEM_OK;
   }
-  return launch_integrate(m, a, v, s);
+  return launch_all(s);
 }
 
 int chem_rhs(const chem_mech* m, int64_t ncells, int64_t ld, const double* state, double p, double* f,

@@ -29,6 +29,7 @@ low            [R,3] f64       lnA0, b0, theta0 of the low-pressure limit
 from __future__ import annotations
 
 import hashlib
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -246,6 +247,7 @@ class Workload:
     majors: int | None = None
     floor: float = 0.0
     notes: str = ""
+    pool: str | None = None  # file of pre-relaxed states to sample cells from
 
     @property
     def N(self):
@@ -257,8 +259,21 @@ class Workload:
 
     def states(self, mech: dict | None = None, n_cells: int | None = None) -> np.ndarray:
         mech = mech if mech is not None else self.mechanism()
+        if self.pool is not None:
+            return pool_states(self.pool, n_cells or self.n_cells, self.state_seed)
         return make_states(mech, n_cells or self.n_cells, self.state_seed, list(self.T_ranges),
                            self.fractions, self.alpha, self.majors, self.floor)
+
+
+POOL_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden")
+
+
+def pool_states(name: str, n_cells: int, seed: int) -> np.ndarray:
+    """n_cells states drawn with replacement from a stored pool [N, P] (a .npy
+    file next to the script that wrote it; see that script for its recipe)."""
+    pool = np.load(os.path.join(POOL_DIR, name), allow_pickle=False)
+    idx = _rng(seed).integers(0, pool.shape[1], size=n_cells)
+    return np.ascontiguousarray(pool[:, idx])
 
 
 ATM = 101325.0
@@ -269,9 +284,11 @@ WORKLOADS = {
     # 54 species / 270 reactions (27 third-body, 14 Troe), 60 bar, stratified states
     "c2_54sp": Workload("c2_54sp", 54, 270, 27, 14, 65536, 60e5, 1e-6,
                         ((700.0, 1000.0), (1800.0, 2600.0)), (0.8, 0.2), 1002, 2002),
-    # batching workload: same mechanism, 262,144 cells, dt 1e-5 s
+    # batching workload: same mechanism, 262,144 cells, dt 1e-5 s, drawn from a
+    # pool of states relaxed for different times (75% near equilibrium, 25%
+    # mid-transient), so step counts span about 1 to 500
     "c3_batch": Workload("c3_batch", 54, 270, 27, 14, 262144, 60e5, 1e-5,
-                         ((700.0, 1000.0), (1000.0, 1600.0)), (0.75, 0.25), 1002, 2003),
+                         ((700.0, 1600.0),), None, 1002, 2003, pool="c3_relaxed_pool.npy"),
     # adjoint workload: 53 species / 325 reactions, 16,384 cells, 1 atm
     "c4_adj": Workload("c4_adj", 53, 325, 32, 16, 16384, ATM, 1e-6, ((1200.0, 2200.0),), None,
                        1004, 2004),
