@@ -75,6 +75,29 @@ def adjoint_flop_model(mech: dict, method_stages: int = 4, new_f: int = 3) -> di
     return dict(f_replay=2 * (fm["f_step"] + fm["f_att"]), f_rev=f_rev, **fm)
 
 
+KERNEL_SOURCES = ("chem_common.hpp", "chem_cell.hpp", "chem.hip")
+
+
+def measured_traffic(workload: str, ncells: int):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources changed since the counters were taken (or no summary
+    covers this workload)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", f"k_integrate_{workload}_hbm.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2105_12070_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    m = {k: v for k, v in re.findall(r"^(\w+): (.+)$", txt, flags=re.M)}
+    if m.get("source_sha256") != h.hexdigest() or m.get("workload") != f"{workload} {ncells}":
+        return None
+    return float(m["fetch_bytes_per_launch"]) + float(m["write_bytes_per_launch"])
+
+
 def cpu_baseline(w, mech, st0, target_s=12.0):
     import oracle
     oracle.build(force=False)
@@ -105,6 +128,8 @@ def main():
     ap.add_argument("--cost-order", action="store_true",
                     help="persistent queue ordered by the previous call's step counts")
     ap.add_argument("--cells", type=int, default=0, help="integrate only the first CELLS cells (profiling)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--adjoint", action="store_true",
                     help="time chem_integrate_adjoint (gradients of sum_cells[T + w.Y] w.r.t. lnA, b, theta)")
     args = ap.parse_args()
@@ -116,6 +141,15 @@ def main():
     import torch
     from paper_2105_12070_amd import chem
 
+    if args.calib_copy_mib:
+        import torch
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.adjoint:
         return bench_adjoint(args)
     w = WORKLOADS[args.config]
@@ -205,7 +239,9 @@ def main():
                    "n_cells": nc, "N": w.N, "variant": variant, "graph": bool(args.graph),
                    "cost_order": bool(args.cost_order)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(w.name, nc),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes": nc * (16 * (w.N + 1) + 12),
                      "kernel_ms": kern_ms, "flops_per_launch": flops},
         "steps_mean": float(sp.mean()), "rejects_mean": float(rj.mean()),
         "steps_percentiles_0_50_90_99_100": np.percentile(sp, [0, 50, 90, 99, 100]).tolist(),
