@@ -94,7 +94,10 @@ typedef struct chem_options {
 int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out);
 void chem_free_mechanism(chem_mech* mech);
 
-/* Largest N the compiled kernels accept, and the mechanism's sizes. */
+/* Largest N the compiled kernels accept (255), and the mechanism's sizes.
+ * N <= 64 runs one cell per wavefront; 64 < N <= 255 runs one cell per
+ * 256-thread workgroup with a blocked LU (chem_integrate_adjoint then returns
+ * CHEM_EUNSUPPORTED, and chem_autotune has a single variant to report). */
 int chem_max_n(void);
 int chem_mech_sizes(const chem_mech* mech, int32_t* K, int32_t* R);
 
@@ -142,7 +145,8 @@ int chem_integrate_adjoint(const chem_mech* mech, int64_t ncells, int64_t ld, co
  * chem_lu_solve : for each of nmat matrices A (device [nmat][n][n] row-major,
  *                 not modified) solves A x = b in place (b device [nmat][n]),
  *                 LU with partial pivoting as LAPACK getrf/getrs (section 2.3);
- *                 info[m] = 0 or the 1-based step of a zero pivot. */
+ *                 info[m] = 0 or the 1-based step of a zero pivot; n <= 256
+ *                 (n > 64 uses the workgroup LU and synchronises the stream). */
 int chem_rhs(const chem_mech* mech, int64_t ncells, int64_t ld, const double* state, double p, double* f,
              void* stream);
 int chem_jacobian(const chem_mech* mech, int64_t ncells, int64_t ld, const double* state, double p, double* J,

@@ -11,6 +11,7 @@
 
 #include "../../include/chem.h"
 #include "chem_adjoint.hpp"
+#include "chem_wg.hpp"
 #include "chem_cell.hpp"
 
 using namespace chem;
@@ -113,6 +114,85 @@ __global__ __launch_bounds__(256) void k_lu_solve(int64_t nmat, int n, const dou
   const double bi = lane < n ? b[(size_t)mi * n + lane] : 0.0;
   const double x = lu_solve<NP>(row, n, lane, src, myrdiag, bi);
   if (lane < n) b[(size_t)mi * n + lane] = x;
+}
+
+// ---------------------------------------------------------------- workgroup path (64 < N <= 256)
+// One cell per 256-thread workgroup; each workgroup owns a scratch slot of two
+// NP x NP matrices.  The grid is persistent (cells come from the queue).
+__global__ __launch_bounds__(WG) void k_integrate_wg(IntArgs a, WgTerms tl, double* scratch, int NP) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  stage_blob(lds, a.blob, a.d.lds_bytes);
+  const MechView m = make_view(lds, a);
+  const WgWs w = make_wg_ws((double*)(lds + a.d.lds_bytes), a.d.R, NP);
+  double* Sx = scratch + (size_t)blockIdx.x * 2 * NP * NP;
+  double* Mx = Sx + (size_t)NP * NP;
+  for (int i = threadIdx.x; i < NP * NP; i += WG) Sx[i] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) w.flag[3] = atomicAdd(a.queue, 1);
+  __syncthreads();
+  int64_t idx = w.flag[3];
+  __syncthreads();
+  while (idx < a.ncells) {
+    const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
+    wg_integrate_cell(m, w, tl, Sx, Mx, NP, a, c);
+    if (threadIdx.x == 0) w.flag[3] = atomicAdd(a.queue, 1);
+    __syncthreads();
+    idx = w.flag[3];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_rhs_jac_wg(IntArgs a, WgTerms tl, double* scratch, int NP, const double* st,
+                                                   double* f, double* J) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  stage_blob(lds, a.blob, a.d.lds_bytes);
+  const MechView m = make_view(lds, a);
+  const WgWs w = make_wg_ws((double*)(lds + a.d.lds_bytes), a.d.R, NP);
+  double* Sx = scratch + (size_t)blockIdx.x * NP * NP;
+  for (int i = threadIdx.x; i < NP * NP; i += WG) Sx[i] = 0.0;
+  __syncthreads();
+  const int t = threadIdx.x, N = m.d.N;
+  for (int64_t c = blockIdx.x; c < a.ncells; c += gridDim.x) {
+    const double y = t < N ? st[(int64_t)t * a.ld + c] : 0.0;
+    double fv;
+    if (J) {
+      fv = wg_jac(m, w, tl, Sx, NP, y, a.p);
+      for (int idx = t; idx < N * N; idx += WG) {
+        const int i = idx / N, j = idx - i * N;
+        double v;
+        if (i == 0) v = w.jTr[j];
+        else if (j == 0) v = w.jT0[i];
+        else v = m.iW[j - 1] * (m.W[i - 1] * (Sx[(size_t)i * NP + j] + w.ad[i]) + w.gam[i]);
+        J[(size_t)c * N * N + idx] = v;
+      }
+    } else {
+      fv = wg_rhs(m, w, y, a.p);
+    }
+    if (f && t < N) f[(int64_t)t * a.ld + c] = fv;
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_lu_wg(int64_t nmat, int n, const double* A, double* b, int32_t* info,
+                                              double* scratch, int NP) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const WgWs w = make_wg_ws((double*)lds, 0, NP);
+  double* Mx = scratch + (size_t)blockIdx.x * NP * NP;
+  const int t = threadIdx.x;
+  for (int64_t mi = blockIdx.x; mi < nmat; mi += gridDim.x) {
+    for (int idx = t; idx < NP * NP; idx += WG) {
+      const int i = idx / NP, j = idx - i * NP;
+      Mx[idx] = (i < n && j < n) ? A[((size_t)mi * n + i) * n + j] : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    const int rc = wg_lu(w, Mx, NP);
+    if (t == 0) info[mi] = rc;
+    if (rc == 0) {
+      const double x = wg_solve(w, Mx, NP, t < n ? b[(size_t)mi * n + t] : 0.0);
+      if (t < n) b[(size_t)mi * n + t] = x;
+    }
+    __syncthreads();
+  }
 }
 
 __global__ void k_set_arrhenius(uint8_t* blob, MechDims d, const int32_t* perm, const double* lnA, const double* b,
@@ -231,6 +311,14 @@ struct chem_mech {
   uint32_t* adj_sent = nullptr;
   int32_t* adj_tptr = nullptr;
   uint32_t* adj_tent = nullptr;
+  // workgroup path (64 < N <= 256): Jacobian term lists and per-workgroup scratch
+  bool wg = false;
+  int wg_np = 0;             // N rounded up to a multiple of 16
+  int32_t* wg_gptr = nullptr;
+  uint32_t* wg_grp = nullptr;
+  uint64_t* wg_term = nullptr;
+  double* wg_scr = nullptr;
+  size_t wg_scr_bytes = 0;
 };
 
 namespace {
@@ -277,7 +365,64 @@ int set_lds_limit(const void* fn, size_t bytes) {
   return 0;
 }
 
+size_t wg_lds_bytes(const chem_mech* m) {
+  return m->d.lds_bytes + (size_t)wg_ws_doubles(m->d.R, m->wg_np) * sizeof(double);
+}
+
+WgTerms wg_terms(const chem_mech* m) {
+  WgTerms t;
+  t.gptr = m->wg_gptr;
+  t.grp = m->wg_grp;
+  t.term = m->wg_term;
+  return t;
+}
+
+// Persistent grid of the workgroup path: one workgroup per CU and LDS slot.
+int wg_grid(const chem_mech* m, int64_t items) {
+  const int per_cu = std::max(1, (int)(m->max_lds / wg_lds_bytes(m)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)m->ncu * per_cu, items));
+}
+
+// Scratch for `slots` workgroups of `mats` NP x NP matrices each (grown lazily;
+// never called during graph capture).
+int ensure_wg_scratch(chem_mech* m, int slots, int mats) {
+  const size_t need = (size_t)slots * mats * m->wg_np * m->wg_np * sizeof(double);
+  if (m->wg_scr_bytes >= need) return 0;
+  hipFree(m->wg_scr);
+  m->wg_scr = nullptr;
+  m->wg_scr_bytes = 0;
+  if (hipMalloc(&m->wg_scr, need) != hipSuccess) return fail(CHEM_ENOMEM, "workgroup scratch allocation failed");
+  m->wg_scr_bytes = need;
+  return 0;
+}
+
+int launch_integrate_wg(chem_mech* m, const IntArgs& a0, hipStream_t s) {
+  IntArgs a = a0;
+  const int grid = wg_grid(m, a.ncells);
+  if ((size_t)grid * 2 * m->wg_np * m->wg_np * sizeof(double) > m->wg_scr_bytes)
+    return fail(CHEM_EINVAL, "workgroup scratch not prepared");
+  const size_t lds = wg_lds_bytes(m);
+  HIPCHK(hipFuncSetAttribute((const void*)k_integrate_wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  a.queue = m->queue;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, m->queue);
+  hipLaunchKernelGGL(k_integrate_wg, dim3(grid), dim3(WG), lds, s, a, wg_terms(m), m->wg_scr, m->wg_np);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int launch_rhs_jac_wg(chem_mech* m, const IntArgs& a, const double* st, double* f, double* J, hipStream_t s) {
+  const int grid = wg_grid(m, a.ncells);
+  const int rc = ensure_wg_scratch(m, grid, 2);
+  if (rc) return rc;
+  const size_t lds = wg_lds_bytes(m);
+  HIPCHK(hipFuncSetAttribute((const void*)k_rhs_jac_wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_rhs_jac_wg, dim3(grid), dim3(WG), lds, s, a, wg_terms(m), m->wg_scr, m->wg_np, st, f, J);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
 int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStream_t s) {
+  if (m->wg) return launch_integrate_wg(m, a0, s);
   IntArgs a = a0;
   const int wpb = std::max(1, std::min(v.wpb, max_wpb(m)));
   if (wpb < 1) return fail(CHEM_EUNSUPPORTED, "mechanism workspace does not fit in LDS");
@@ -333,7 +478,7 @@ extern "C" {
 
 const char* chem_last_error(void) { return g_err.c_str(); }
 
-int chem_max_n(void) { return 64; }
+int chem_max_n(void) { return 255; }
 
 int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   if (!desc || !out) return fail(CHEM_EINVAL, "null descriptor or output pointer");
@@ -345,7 +490,8 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
                                              !desc->b || !desc->theta)))
     return fail(CHEM_EINVAL, "missing mechanism array");
   const int N = K + 1;
-  if (np_for(N) == 0) return fail(CHEM_EUNSUPPORTED, "state size N = " + std::to_string(N) + " exceeds the compiled limit 64");
+  const bool wg = np_for(N) == 0;  // N > 64: one cell per workgroup
+  if (wg && R >= 65536) return fail(CHEM_EUNSUPPORTED, "more than 65535 reactions for N > 64");
   for (int k = 0; k < K; ++k)
     if (!(desc->W[k] > 0.0) || !std::isfinite(desc->W[k])) return fail(CHEM_EINVAL, "molar masses must be positive");
   if (!finite_all(desc->nasa7, (size_t)15 * K)) return fail(CHEM_EINVAL, "non-finite NASA-7 coefficient");
@@ -378,7 +524,7 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   d.K = K;
   d.R = R;
   d.N = N;
-  d.S = np_for(N) + 1;  // odd (NP is a multiple of 8), with padding columns after N
+  d.S = wg ? N + 1 : np_for(N) + 1;  // odd (NP is a multiple of 8), with padding columns after N
   d.R0 = R0;
   d.R1 = R1;
   // species -> (reaction, net nu) incidence, ascending internal reaction index
@@ -514,8 +660,45 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   tptr[K] = (int32_t)tent.size();
   if (sent.empty()) sent.push_back(0);
   if (tent.empty()) tent.push_back(0);
+  // workgroup-path Jacobian terms: per species row, groups by column, terms in a fixed order
+  std::vector<int32_t> wgptr;
+  std::vector<uint32_t> wgrp;
+  std::vector<uint64_t> wterm;
+  if (wg) {
+    wgptr.assign(K + 1, 0);
+    for (int k = 0; k < K; ++k) {
+      wgptr[k] = (int32_t)wgrp.size();
+      std::vector<std::vector<uint64_t>> bycol(K);
+      for (int e = cptr[k]; e < cptr[k + 1]; ++e) {
+        const int ri = (int)(cent[e] >> 8);
+        const uint64_t nu8 = (uint64_t)(uint8_t)(cent[e] & 0xFF);
+        uint64_t sl[6];
+        for (int q = 0; q < 6; ++q) sl[q] = (sp[ri] >> (8 * q)) & 0xFF;
+        for (int q = 0; q < 6; ++q) {
+          if ((int)sl[q] >= K) continue;
+          const int b0 = q < 3 ? 0 : 3;
+          const int qa = b0 + (q - b0 == 0 ? 1 : 0), qb = b0 + (q - b0 == 2 ? 1 : 2);
+          bycol[sl[q]].push_back((uint64_t)ri | ((uint64_t)q << 16) | (nu8 << 24) | (sl[qa] << 32) | (sl[qb] << 40));
+        }
+        if (ri >= R0)
+          for (int te = tbp[ri - R0]; te < tbp[ri - R0 + 1]; ++te)
+            bycol[tbs[te]].push_back((uint64_t)ri | (6ull << 16) | (nu8 << 24) | ((uint64_t)te << 48));
+      }
+      for (int l = 0; l < K; ++l) {
+        if (bycol[l].empty()) continue;
+        wgrp.push_back(((uint32_t)wterm.size() << 8) | (uint32_t)l);
+        wterm.insert(wterm.end(), bycol[l].begin(), bycol[l].end());
+      }
+    }
+    wgptr[K] = (int32_t)wgrp.size();
+    wgrp.push_back((uint32_t)wterm.size() << 8);
+    if (wterm.size() >= (1u << 24)) return fail(CHEM_EUNSUPPORTED, "too many Jacobian terms");
+    if (wterm.empty()) wterm.push_back(0);
+  }
   chem_mech* m = new chem_mech();
   m->d = d;
+  m->wg = wg;
+  m->wg_np = wg ? ((N + 15) / 16) * 16 : 0;
   m->h_perm.assign(order.begin(), order.end());
   auto cleanup = [&](int code, const std::string& msg) {
     chem_free_mechanism(m);
@@ -524,8 +707,19 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   if (hipGetDevice(&m->device) != hipSuccess) return cleanup(CHEM_EHIP, "hipGetDevice failed");
   hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, m->device);
   hipDeviceGetAttribute(&m->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
-  if (m->max_lds < d.lds_bytes + (int)cell_bytes(d))
+  if (!wg && m->max_lds < d.lds_bytes + (int)cell_bytes(d))
     return cleanup(CHEM_EUNSUPPORTED, "mechanism workspace needs more LDS than one workgroup has");
+  if (wg && (size_t)m->max_lds < wg_lds_bytes(m))
+    return cleanup(CHEM_EUNSUPPORTED, "mechanism tables and the workgroup workspace need more LDS than a workgroup has");
+  if (wg) {
+    if (hipMalloc(&m->wg_gptr, 4 * wgptr.size()) != hipSuccess || hipMalloc(&m->wg_grp, 4 * wgrp.size()) != hipSuccess ||
+        hipMalloc(&m->wg_term, 8 * wterm.size()) != hipSuccess)
+      return cleanup(CHEM_ENOMEM, "device allocation failed");
+    if (hipMemcpy(m->wg_gptr, wgptr.data(), 4 * wgptr.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->wg_grp, wgrp.data(), 4 * wgrp.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->wg_term, wterm.data(), 8 * wterm.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(CHEM_EHIP, "upload failed");
+  }
   if (hipMalloc(&m->blob, blob.size()) != hipSuccess || hipMalloc(&m->nasa, 8 * nasa.size()) != hipSuccess ||
       hipMalloc(&m->perm, 4 * (size_t)std::max(R, 1)) != hipSuccess || hipMalloc(&m->queue, 64) != hipSuccess ||
       hipMalloc(&m->adj_sptr, 4 * sptr.size()) != hipSuccess || hipMalloc(&m->adj_sent, 4 * sent.size()) != hipSuccess ||
@@ -556,6 +750,10 @@ void chem_free_mechanism(chem_mech* m) {
   hipFree(m->adj_ws);
   hipFree(m->order);
   hipFree(m->order_cnt);
+  hipFree(m->wg_gptr);
+  hipFree(m->wg_grp);
+  hipFree(m->wg_term);
+  hipFree(m->wg_scr);
   hipFree(m->adj_sptr);
   hipFree(m->adj_sent);
   hipFree(m->adj_tptr);
@@ -654,6 +852,10 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
       return fail(CHEM_ENOMEM, "cost-order counter allocation failed");
   }
   if (ordered) a.order = m->order;
+  if (m->wg) {
+    const int rc = ensure_wg_scratch(m, wg_grid(m, ncells), 2);
+    if (rc) return rc;
+  }
   auto launch_all = [&](hipStream_t st) -> int {
     if (ordered) {
       const int rc = launch_order(m, steps, ncells, st);
@@ -665,7 +867,7 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
     GraphKey key;
     key.v = {(uintptr_t)state, (uintptr_t)h, (uintptr_t)ncells, (uintptr_t)ld, (uintptr_t)steps,
              (uintptr_t)rejects, (uintptr_t)status, (uintptr_t)s, (uintptr_t)v.wpb, (uintptr_t)v.grid_mult,
-             (uintptr_t)ordered, (uintptr_t)m->order};
+             (uintptr_t)ordered, (uintptr_t)m->order, (uintptr_t)m->wg_scr};
     double dv[5] = {p, dt, rtol, atol, (double)(opt ? opt->method : 0)};
     for (double x : dv) {
       uint64_t u;
@@ -703,6 +905,7 @@ int chem_rhs(const chem_mech* m, int64_t ncells, int64_t ld, const double* state
   a.ld = ld;
   a.ncells = ncells;
   a.p = 10.0 * p;
+  if (m->wg) return launch_rhs_jac_wg(const_cast<chem_mech*>(m), a, state, f, nullptr, (hipStream_t)stream);
   const int wpb = std::max(1, std::min(4, max_wpb(m)));
   const size_t lds = m->d.lds_bytes + (size_t)wpb * cell_bytes(m->d);
   return with_np(m->d.N, [&](auto npc) -> int {
@@ -724,6 +927,7 @@ int chem_jacobian(const chem_mech* m, int64_t ncells, int64_t ld, const double* 
   a.ld = ld;
   a.ncells = ncells;
   a.p = 10.0 * p;
+  if (m->wg) return launch_rhs_jac_wg(const_cast<chem_mech*>(m), a, state, f, J, (hipStream_t)stream);
   const int wpb = std::max(1, std::min(4, max_wpb(m)));
   const size_t lds = m->d.lds_bytes + (size_t)wpb * cell_bytes(m->d);
   return with_np(m->d.N, [&](auto npc) -> int {
@@ -740,6 +944,28 @@ int chem_lu_solve(int64_t nmat, int32_t n, const double* A, double* b, int32_t* 
   if (nmat < 0 || n < 1) return fail(CHEM_EINVAL, "need nmat >= 0 and n >= 1");
   if (nmat == 0) return CHEM_OK;
   if (!A || !b || !info) return fail(CHEM_EINVAL, "null argument");
+  if (n > 64) {
+    if (n > 256) return fail(CHEM_EUNSUPPORTED, "n > 256");
+    // workgroup LU: one matrix per 256-thread workgroup, NP x NP scratch each
+    const int NP = ((n + 15) / 16) * 16;
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int grid = (int)std::min<int64_t>(nmat, std::max(ncu, 1));
+    double* scr = nullptr;
+    if (hipMalloc(&scr, sizeof(double) * (size_t)grid * NP * NP) != hipSuccess)
+      return fail(CHEM_ENOMEM, "LU scratch allocation failed");
+    const size_t lds = (size_t)wg_ws_doubles(0, NP) * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void*)k_lu_wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_lu_wg, dim3(grid), dim3(WG), lds, (hipStream_t)stream, nmat, n, A, b, info, scr, NP);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    hipFree(scr);
+    if (e != hipSuccess) return fail(CHEM_EHIP, std::string("workgroup LU: ") + hipGetErrorString(e));
+    return CHEM_OK;
+  }
   return with_np(n, [&](auto npc) -> int {
     constexpr int NP = decltype(npc)::value;
     hipLaunchKernelGGL(k_lu_solve<NP>, dim3((nmat + 3) / 4), dim3(256), 0, (hipStream_t)stream, nmat, n, A, b, info);
@@ -752,6 +978,15 @@ int chem_autotune(chem_mech* m, int64_t ncells, int64_t ld, const double* state,
                   double dt, double rtol, double atol, int32_t* out_variant, double* out_ms, void* stream) {
   if (!m || !state || !h) return fail(CHEM_EINVAL, "null argument");
   if (ncells < 1 || ld < ncells) return fail(CHEM_EINVAL, "need 1 <= ncells <= ld");
+  if (m->wg) {  // the workgroup path has a single launch shape
+    if (out_variant) {
+      out_variant[0] = 1;
+      out_variant[1] = 1;
+      out_variant[2] = 1;
+    }
+    if (out_ms) *out_ms = 0.0;
+    return CHEM_OK;
+  }
   const int N = m->d.N;
   hipStream_t s = (hipStream_t)stream;
   double *st = nullptr, *hh = nullptr;

@@ -259,11 +259,21 @@ __device__ inline double rhs(const MechView& m, const CellWs& w, double y, doubl
   double om = 0.0;
   if (isSp) {
     const int k = lane - 1;
+    const int e0 = m.cptr[k], e1 = m.cptr[k + 1];
+    // two independent partial sums, combined in a fixed order
+    double om1 = 0.0;
+    int e = e0;
 #pragma clang loop unroll(disable)
-    for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
-      const uint32_t v = m.cent[e];
-      om += (double)(int8_t)(v & 0xFF) * w.rk[v >> 8];
+    for (; e + 2 <= e1; e += 2) {
+      const uint32_t v0 = m.cent[e], v1 = m.cent[e + 1];
+      om += (double)(int8_t)(v0 & 0xFF) * w.rk[v0 >> 8];
+      om1 += (double)(int8_t)(v1 & 0xFF) * w.rk[v1 >> 8];
     }
+    if (e < e1) {
+      const uint32_t v0 = m.cent[e];
+      om += (double)(int8_t)(v0 & 0xFF) * w.rk[v0 >> 8];
+    }
+    om += om1;
   }
   const double Q = wave_sum(isSp ? t.hRT * om : 0.0);
   const double fT = -RU * x.T * Q * x.iRho / x.cp;
@@ -332,12 +342,21 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
   double om = 0.0, dwdT = 0.0, adense = 0.0;
   if (isSp) {
     const int k = lane - 1;
+    const int e0 = m.cptr[k], e1 = m.cptr[k + 1];
+    // the next entry's table words are loaded one iteration ahead
+    uint32_t vnext = e0 < e1 ? m.cent[e0] : 0u;
+    uint64_t snext = e0 < e1 ? m.sp[vnext >> 8] : 0ull;
 #pragma clang loop unroll(disable)
-    for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
-      const uint32_t v = m.cent[e];
+    for (int e = e0; e < e1; ++e) {
+      const uint32_t v = vnext;
+      const uint64_t sw = snext;
+      if (e + 1 < e1) {
+        vnext = m.cent[e + 1];
+        snext = m.sp[vnext >> 8];
+      }
       const int r = (int)(v >> 8);
       const double nu = (double)(int8_t)(v & 0xFF);
-      const Slots s = unpack(m.sp[r]);
+      const Slots s = unpack(sw);
       const double c0 = w.C[s.r0], c1 = w.C[s.r1], c2 = w.C[s.r2];
       const double d0 = w.C[s.p0], d1 = w.C[s.p1], d2 = w.C[s.p2];
       const double kf = w.rk[r], kr = w.rkr[r];
@@ -483,8 +502,23 @@ __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep,
       c2 = fma(-l, u2, c2);
       c3 = fma(-l, u3, c3);
       c0 = upd ? l : c0;
+      if (BCAST_LDS) {
 #pragma unroll
-      for (int j = k0 + 4; j < NP; ++j) row[j] = fma(-l, BCAST_LDS ? bc[j - k0] : readlane(row[j], p), row[j]);
+        for (int j = k0 + 4; j < NP; ++j) row[j] = fma(-l, bc[j - k0], row[j]);
+      } else {
+        // four broadcasts in flight before their four FMAs: the scalar
+        // registers differ, so no broadcast waits on the previous FMA
+#pragma unroll
+        for (int j = k0 + 4; j < NP; j += 4) {
+          const double u0 = readlane(row[j], p), v1 = readlane(row[j + 1], p);
+          const double v2 = readlane(row[j + 2], p), v3 = readlane(row[j + 3], p);
+          __builtin_amdgcn_sched_barrier(0);
+          row[j] = fma(-l, u0, row[j]);
+          row[j + 1] = fma(-l, v1, row[j + 1]);
+          row[j + 2] = fma(-l, v2, row[j + 2]);
+          row[j + 3] = fma(-l, v3, row[j + 3]);
+        }
+      }
       if (BCAST_LDS) wsync();
       const double t = c0;
       c0 = c1;

@@ -1,0 +1,693 @@
+// Device solver for one cell per 256-thread workgroup (64 < N <= 256).
+//
+// Thread t owns component t of every state-sized vector (t = 0 is T, t = 1+k
+// is Y_k).  The iteration matrix M = I/(gamma h) - J of a 151-species cell
+// (182 KB) does not fit in LDS, so each workgroup keeps two NP x NP FP64
+// matrices in a global scratch slot (L2/MALL resident while the cell is
+// worked on): Sx, the sparse part of d omega/dC at its structural positions,
+// and Mx, the matrix being factored.  The LU is blocked by 16 columns: the
+// panel is factored in LDS by one wave (partial pivoting, first largest |a|),
+// its row interchanges are applied to the other columns, the 16 rows of U are
+// formed by a triangular solve, and the trailing matrix takes one rank-16
+// update per panel (4 x 4 register blocks, operands from LDS).  The Jacobian
+// is assembled without atomics: every species row walks a host-built list of
+// its nonzero columns, each with the reaction terms that contribute to it, in
+// a fixed order.  All sums over threads are fixed-order, so results are
+// bitwise reproducible.
+#pragma once
+#include "chem_cell.hpp"
+
+namespace chem {
+
+constexpr int WG = 256;  // threads per workgroup (4 waves)
+constexpr int WNB = 16;  // panel width of the blocked LU
+
+// Jacobian term lists of the workgroup path (global memory, built by the
+// loader).  Row k (species k) owns groups [gptr[k], gptr[k+1]); group g covers
+// terms [grp[g] >> 8, grp[g+1] >> 8) and column species (grp[g] & 0xFF).  A
+// term is packed as: bits 0-15 reaction, 16-18 kind (0-2 reactant slot, 3-5
+// product slot, 6 third-body efficiency), 24-31 nu (int8), 32-39 and 40-47 the
+// two other molecules of that side (K = padding), 48-59 efficiency entry.
+struct WgTerms {
+  const int32_t* gptr;  // [K+1]
+  const uint32_t* grp;  // [G+1] (sentinel at G)
+  const uint64_t* term; // [T]
+};
+
+// Per-workgroup LDS workspace (beyond the staged mechanism blob); NP = N
+// rounded up to a multiple of 16.
+struct WgWs {
+  double* C;     // [NP] concentrations, C[K] = 1
+  double* g;     // [NP] g/RT
+  double* hR;    // [NP] h/RT
+  double* rk;    // [R]
+  double* rkr;   // [R]
+  double* rdm;   // [R]
+  double* rdt;   // [R]
+  double* vec;   // [NP] state-sized exchange vector (y for thermo, b for solves)
+  double* ad;    // [NP] adense_k per state row (row 1+k)
+  double* gam;   // [NP]
+  double* jT0;   // [NP] column 0 of J (J_iT)
+  double* jTr;   // [NP] row 0 of J (J_Tj)
+  double* Pn;    // [NP * 16] panel
+  double* Ub;    // [16 * NP] rows of U of the panel
+  double* rdg;   // [NP] 1 / U_kk
+  double* red;   // [16] block reduction scratch
+  int* piv;      // [NP] row interchanges of the LU
+  int* perm;     // [NP] their composition (row i of P M is row perm[i] of M)
+  int* flag;     // [4] flags and the queue broadcast
+};
+
+__host__ __device__ inline int wg_ws_doubles(int R, int NP) { return 4 * R + 9 * NP + 2 * WNB * NP + 16 + NP + 4; }
+
+__device__ inline WgWs make_wg_ws(double* base, int R, int NP) {
+  WgWs w;
+  w.C = base;
+  w.g = w.C + NP;
+  w.hR = w.g + NP;
+  w.rk = w.hR + NP;
+  w.rkr = w.rk + R;
+  w.rdm = w.rkr + R;
+  w.rdt = w.rdm + R;
+  w.vec = w.rdt + R;
+  w.ad = w.vec + NP;
+  w.gam = w.ad + NP;
+  w.jT0 = w.gam + NP;
+  w.jTr = w.jT0 + NP;
+  w.Pn = w.jTr + NP;
+  w.Ub = w.Pn + NP * WNB;
+  w.rdg = w.Ub + NP * WNB;
+  w.red = w.rdg + NP;
+  w.piv = (int*)(w.red + 16);
+  w.perm = w.piv + NP;
+  w.flag = w.perm + NP;
+  return w;
+}
+
+// CellWs view of the workgroup workspace for the shared rate helpers.
+__device__ inline CellWs wg_cellws(const WgWs& w) {
+  CellWs c{};
+  c.rk = w.rk;
+  c.rkr = w.rkr;
+  c.rdm = w.rdm;
+  c.rdt = w.rdt;
+  c.C = w.C;
+  c.g = w.g;
+  c.hR = w.hR;
+  return c;
+}
+
+// Sum over the workgroup in a fixed order (wave sums, then the four partials
+// in wave order); every thread gets the result.
+__device__ inline double block_sum(double v, double* red) {
+  const double s = wave_sum(v);
+  const int wv = threadIdx.x / WAVE;
+  if ((threadIdx.x & (WAVE - 1)) == 0) red[wv] = s;
+  __syncthreads();
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return r;
+}
+
+__device__ inline bool block_any(bool p, int* flag) {
+  if (threadIdx.x == 0) flag[0] = 0;
+  __syncthreads();
+  if (p) flag[0] = 1;  // benign race: every writer stores 1
+  __syncthreads();
+  const bool r = flag[0] != 0;
+  __syncthreads();
+  return r;
+}
+
+// Thermo and mixture of the state in w.vec; fills C, g, hR; returns the
+// thread's species thermo (species k = t - 1 for 1 <= t <= K).
+__device__ inline SpThermo wg_species(const MechView& m, const WgWs& w, double p, Mix& x, double& Yk) {
+  const int K = m.d.K, t = threadIdx.x;
+  const bool isSp = t >= 1 && t <= K;
+  const int k = isSp ? t - 1 : 0;
+  x.T = w.vec[0];
+  x.lnT = log(x.T);
+  x.iT = 1.0 / x.T;
+  const SpThermo th = nasa7(m.nasa + 16 * k, x.T, x.lnT, x.iT);
+  Yk = isSp ? w.vec[t] : 0.0;
+  const double iWk = m.iW[k];
+  const double yw = Yk * iWk;
+  const double sy = block_sum(yw, w.red);
+  x.Wbar = 1.0 / sy;
+  x.rho = p * x.Wbar * x.iT / RU;
+  x.iRho = 1.0 / x.rho;
+  x.Ctot = p * x.iT / RU;
+  x.lnPRT = log(PATM * x.iT / RU);
+  x.cp = block_sum(isSp ? Yk * th.cpR * RU * iWk : 0.0, w.red);
+  if (isSp) {
+    w.C[k] = x.rho * yw;
+    w.g[k] = th.hRT - th.sR;
+    w.hR[k] = th.hRT;
+  }
+  if (t == 0) {
+    w.C[K] = 1.0;
+    w.g[K] = 0.0;
+    w.hR[K] = 0.0;
+  }
+  __syncthreads();
+  return th;
+}
+
+// f(y) with y_t held by thread t; returns f_t.
+__device__ inline double wg_rhs(const MechView& m, const WgWs& w, double y, double p) {
+  const int K = m.d.K, R = m.d.R, N = m.d.N, t = threadIdx.x;
+  if (t < N) w.vec[t] = y;
+  __syncthreads();
+  Mix x;
+  double Yk;
+  const SpThermo th = wg_species(m, w, p, x, Yk);
+  const CellWs cw = wg_cellws(w);
+#pragma clang loop unroll(disable)
+  for (int r = t; r < R; r += WG) {
+    const Slots s = unpack(m.sp[r]);
+    const double lnkf = m.lnA[r] + m.b[r] * x.lnT - m.th[r] * x.iT;
+    const double Rf = w.C[s.r0] * w.C[s.r1] * w.C[s.r2];
+    const double Rr = w.C[s.p0] * w.C[s.p1] * w.C[s.p2];
+    const double sng = w.g[s.p0] + w.g[s.p1] + w.g[s.p2] - w.g[s.r0] - w.g[s.r1] - w.g[s.r2];
+    const double kf = exp(lnkf);
+    const double iKc = exp(sng - s.dnu * x.lnPRT);
+    double q = kf * (Rf - iKc * Rr);
+    if (r >= m.d.R0) {
+      const double M = third_body(m, cw, r, x.Ctot);
+      if (r < m.d.R1) {
+        q *= M;
+      } else {
+        double dk, dl;
+        q = troe_k<false>(m, r, x, kf, 0.0, M, dk, dl) * (Rf - iKc * Rr);
+      }
+    }
+    w.rk[r] = q;
+  }
+  __syncthreads();
+  const bool isSp = t >= 1 && t <= K;
+  double om = 0.0;
+  if (isSp) {
+    const int k = t - 1;
+#pragma clang loop unroll(disable)
+    for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
+      const uint32_t v = m.cent[e];
+      om += (double)(int8_t)(v & 0xFF) * w.rk[v >> 8];
+    }
+  }
+  const double Q = block_sum(isSp ? th.hRT * om : 0.0, w.red);
+  const double fT = -RU * x.T * Q * x.iRho / x.cp;
+  if (t == 0) return fT;
+  return isSp ? m.W[t - 1] * om * x.iRho : 0.0;
+}
+
+// Analytic Jacobian (the same formulas as the wavefront path): the sparse
+// part of d omega/dC goes to Sx at its structural positions (row 1+k, column
+// 1+l), the dense row/column pieces to LDS vectors.  Returns f_t.
+__device__ inline double wg_jac(const MechView& m, const WgWs& w, const WgTerms& tl, double* Sx, int NP, double y,
+                                double p) {
+  const int K = m.d.K, R = m.d.R, N = m.d.N, t = threadIdx.x;
+  if (t < N) w.vec[t] = y;
+  __syncthreads();
+  Mix x;
+  double Yk;
+  const SpThermo th = wg_species(m, w, p, x, Yk);
+  const CellWs cw = wg_cellws(w);
+#pragma clang loop unroll(disable)
+  for (int r = t; r < R; r += WG) {
+    const Slots s = unpack(m.sp[r]);
+    const double lnkf = m.lnA[r] + m.b[r] * x.lnT - m.th[r] * x.iT;
+    const double Rf = w.C[s.r0] * w.C[s.r1] * w.C[s.r2];
+    const double Rr = w.C[s.p0] * w.C[s.p1] * w.C[s.p2];
+    const double sng = w.g[s.p0] + w.g[s.p1] + w.g[s.p2] - w.g[s.r0] - w.g[s.r1] - w.g[s.r2];
+    const double snh = w.hR[s.p0] + w.hR[s.p1] + w.hR[s.p2] - w.hR[s.r0] - w.hR[s.r1] - w.hR[s.r2];
+    const double kf = exp(lnkf);
+    const double iKc = exp(sng - s.dnu * x.lnPRT);
+    const double dlnkf = m.b[r] * x.iT + m.th[r] * x.iT * x.iT;
+    const double dlnKc = (snh - (double)s.dnu) * x.iT;
+    const double net = Rf - iKc * Rr;
+    double keff = kf, dkM = 0.0, dqdT;
+    if (r < m.d.R0) {
+      dqdT = kf * (dlnkf * Rf - iKc * (dlnkf - dlnKc) * Rr);
+    } else {
+      const double M = third_body(m, cw, r, x.Ctot);
+      if (r < m.d.R1) {
+        keff = kf * M;
+        dkM = kf * net;
+        dqdT = M * kf * (dlnkf * Rf - iKc * (dlnkf - dlnKc) * Rr);
+      } else {
+        double dlnk;
+        keff = troe_k<true>(m, r, x, kf, dlnkf, M, dkM, dlnk);
+        dkM *= net;
+        dqdT = keff * (dlnk * net + iKc * Rr * dlnKc);
+      }
+    }
+    w.rk[r] = keff;
+    w.rkr[r] = keff * iKc;
+    w.rdm[r] = dkM;
+    w.rdt[r] = dqdT;
+  }
+  __syncthreads();
+  const bool isSp = t >= 1 && t <= K;
+  double om = 0.0, dwdT = 0.0, adense = 0.0, sk = 0.0;
+  if (isSp) {
+    const int k = t - 1;
+#pragma clang loop unroll(disable)
+    for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
+      const uint32_t v = m.cent[e];
+      const int r = (int)(v >> 8);
+      const double nu = (double)(int8_t)(v & 0xFF);
+      const Slots s = unpack(m.sp[r]);
+      om += nu * (w.rk[r] * w.C[s.r0] * w.C[s.r1] * w.C[s.r2] - w.rkr[r] * w.C[s.p0] * w.C[s.p1] * w.C[s.p2]);
+      dwdT += nu * w.rdt[r];
+      if (r >= m.d.R0) adense += nu * w.rdm[r];
+    }
+    // structural nonzeros of row k, one group per column, terms in a fixed order
+    double* Srow = Sx + (size_t)t * NP + 1;
+    const int g1 = tl.gptr[k + 1];
+#pragma clang loop unroll(disable)
+    for (int gi = tl.gptr[k]; gi < g1; ++gi) {
+      const uint32_t gw = tl.grp[gi];
+      const int col = (int)(gw & 0xFF);
+      const int t1 = (int)(tl.grp[gi + 1] >> 8);
+      double acc = 0.0;
+#pragma clang loop unroll(disable)
+      for (int ti = (int)(gw >> 8); ti < t1; ++ti) {
+        const uint64_t tw = tl.term[ti];
+        const int r = (int)(tw & 0xFFFF);
+        const int kind = (int)((tw >> 16) & 7);
+        const double nu = (double)(int8_t)((tw >> 24) & 0xFF);
+        const double co = w.C[(tw >> 32) & 0xFF] * w.C[(tw >> 40) & 0xFF];
+        double v;
+        if (kind < 3) v = w.rk[r] * co;
+        else if (kind < 6) v = -w.rkr[r] * co;
+        else v = w.rdm[r] * m.tbd[(tw >> 48) & 0xFFF];
+        acc += nu * v;
+      }
+      Srow[col] = acc;
+      sk += w.C[col] * acc;
+    }
+  }
+  // sk = sum_l C_l (S_kl + adense_k); C sums to Ctot
+  if (isSp) {
+    double csum = 0.0;
+    for (int l = 0; l < K; ++l) csum += w.C[l];  // same order on every thread
+    sk += adense * csum;
+  }
+  double fk = 0.0, gam = 0.0, hmW = 0.0, jkT = 0.0;
+  if (isSp) {
+    const int k = t - 1;
+    const double Wk = m.W[k];
+    gam = Wk * x.Wbar * x.iRho * (om - sk);
+    jkT = Wk * x.iRho * (dwdT - sk * x.iT + om * x.iT);
+    fk = Wk * om * x.iRho;
+    hmW = RU * x.T * th.hRT;  // mass enthalpy times W_k
+  }
+  if (t < NP) {
+    w.ad[t] = isSp ? adense : 0.0;
+    w.gam[t] = gam;
+    w.jT0[t] = jkT;
+  }
+  const double Q = block_sum(isSp ? th.hRT * om : 0.0, w.red);
+  const double fT = -RU * x.T * Q * x.iRho / x.cp;
+  const double cpm = isSp ? RU * th.cpR * m.iW[t - 1] : 0.0;
+  const double s1 = block_sum(cpm * fk, w.red);
+  const double dcpdT = block_sum(isSp ? Yk * RU * th.dcpR * m.iW[t - 1] : 0.0, w.red);
+  const double sA = block_sum(hmW * adense, w.red);
+  const double sG = block_sum(isSp ? hmW * m.iW[t - 1] * gam : 0.0, w.red);
+  const double sT = block_sum(isSp ? hmW * m.iW[t - 1] * jkT : 0.0, w.red);
+  // Sx rows are complete (the block sums above synchronised the workgroup)
+  __threadfence_block();
+  __syncthreads();
+  // row 0 of J: column sums of the species rows weighted by mass enthalpy
+  if (isSp) {
+    const int l = t - 1;
+    double cs = 0.0;
+    const double* Sc = Sx + NP + 1 + l;
+#pragma clang loop unroll(disable)
+    for (int k = 0; k < K; ++k) cs += (RU * x.T * w.hR[k]) * Sc[(size_t)k * NP];
+    const double colsum = m.iW[l] * (cs + sA + sG);
+    w.jTr[t] = -(colsum + fT * cpm) / x.cp;
+  } else if (t == 0) {
+    w.jTr[0] = -(sT + s1 + fT * dcpdT) / x.cp;
+  }
+  __syncthreads();
+  return t == 0 ? fT : fk;
+}
+
+// M = I/(gamma h) - J into Mx (NP x NP, identity on the padding); returns
+// false if an entry is not finite.
+__device__ inline bool wg_form(const MechView& m, const WgWs& w, const double* Sx, double* Mx, int NP, double d) {
+  const int N = m.d.N;
+  bool bad = false;
+#pragma clang loop unroll(disable)
+  for (int idx = threadIdx.x; idx < NP * NP; idx += WG) {
+    const int i = idx / NP, j = idx - i * NP;
+    double v;
+    if (i >= N || j >= N) {
+      v = i == j ? 1.0 : 0.0;
+    } else {
+      double J;
+      if (i == 0) J = w.jTr[j];
+      else if (j == 0) J = w.jT0[i];
+      else J = m.iW[j - 1] * (m.W[i - 1] * (Sx[idx] + w.ad[i]) + w.gam[i]);
+      v = (i == j ? d : 0.0) - J;
+      bad |= !__builtin_isfinite(v);
+    }
+    Mx[idx] = v;
+  }
+  return !block_any(bad, w.flag + 1);
+}
+
+// Blocked LU with partial pivoting of Mx in place.  Returns the 1-based step
+// of a zero pivot column, or 0.  Leaves piv, perm and 1/U_kk in LDS.
+__device__ inline int wg_lu(const WgWs& w, double* Mx, int NP) {
+  const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+  if (t == 0) w.flag[2] = 0;
+#pragma clang loop unroll(disable)
+  for (int p0 = 0; p0 < NP; p0 += WNB) {
+    const int nrow = NP - p0;
+    // panel to LDS
+#pragma clang loop unroll(disable)
+    for (int idx = t; idx < nrow * WNB; idx += WG) w.Pn[idx] = Mx[(size_t)(p0 + idx / WNB) * NP + p0 + (idx % WNB)];
+    __syncthreads();
+    if (wv == 0) {
+#pragma clang loop unroll(disable)
+      for (int kk = 0; kk < WNB; ++kk) {
+        const int k = p0 + kk;
+        // first row with the largest |a| in column kk among rows >= k
+        double best = -1.0;
+        int bi = NP;
+        for (int i = k + lane; i < NP; i += WAVE) {
+          const double v = fabs(w.Pn[(i - p0) * WNB + kk]);
+          if (v > best) {
+            best = v;
+            bi = i;
+          }
+        }
+        unsigned long long key = __builtin_bit_cast(unsigned long long, best < 0.0 ? 0.0 : best);
+        unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
+        // wave max of the 64-bit key (non-negative doubles order as integers)
+        unsigned mh = wave_max_u32(hi);
+        unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
+        const bool mine = hi == mh && lo == ml && best >= 0.0;
+        int cand = mine ? bi : NP;
+        // smallest row index among the lanes holding the maximum
+        for (int o = 32; o >= 1; o >>= 1) cand = min(cand, __shfl_xor(cand, o));
+        const int pr = uniform_int(cand);
+        const double pv = (pr < NP) ? w.Pn[(pr - p0) * WNB + kk] : 0.0;
+        const bool sing = !(pv != 0.0);
+        if (lane == 0) {
+          w.piv[k] = sing ? k : pr;
+          if (sing && w.flag[2] == 0) w.flag[2] = k + 1;
+        }
+        const int prow = sing ? k : pr;
+        // swap rows k and prow of the panel
+        if (lane < WNB && prow != k) {
+          const double a = w.Pn[(k - p0) * WNB + lane], b = w.Pn[(prow - p0) * WNB + lane];
+          w.Pn[(k - p0) * WNB + lane] = b;
+          w.Pn[(prow - p0) * WNB + lane] = a;
+        }
+        wsync();
+        const double rp = sing ? 0.0 : 1.0 / pv;
+        if (lane == 0) w.rdg[k] = rp;
+        // multipliers and the rank-1 update of the panel's remaining columns
+        for (int i = k + 1 + lane; i < NP; i += WAVE) {
+          double* Pr = w.Pn + (i - p0) * WNB;
+          const double l = Pr[kk] * rp;
+          Pr[kk] = l;
+          for (int c = kk + 1; c < WNB; ++c) Pr[c] = fma(-l, w.Pn[(k - p0) * WNB + c], Pr[c]);
+        }
+        wsync();
+      }
+    }
+    __syncthreads();
+    // row interchanges on the columns outside the panel (each thread owns
+    // whole columns, so the sequence of swaps stays ordered per column)
+#pragma clang loop unroll(disable)
+    for (int j = t; j < NP; j += WG) {
+      if (j >= p0 && j < p0 + WNB) continue;
+      for (int kk = 0; kk < WNB; ++kk) {
+        const int k = p0 + kk, pr = w.piv[k];
+        if (pr != k) {
+          const double a = Mx[(size_t)k * NP + j], b = Mx[(size_t)pr * NP + j];
+          Mx[(size_t)k * NP + j] = b;
+          Mx[(size_t)pr * NP + j] = a;
+        }
+      }
+      // rows of U of this panel: U12 = L11^-1 A12 (column j, forward substitution)
+      if (j >= p0 + WNB) {
+        double u[WNB];
+#pragma unroll
+        for (int r = 0; r < WNB; ++r) u[r] = Mx[(size_t)(p0 + r) * NP + j];
+#pragma unroll
+        for (int r = 1; r < WNB; ++r) {
+#pragma unroll
+          for (int c = 0; c < r; ++c) u[r] = fma(-w.Pn[r * WNB + c], u[c], u[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < WNB; ++r) {
+          w.Ub[r * NP + j] = u[r];
+          Mx[(size_t)(p0 + r) * NP + j] = u[r];
+        }
+      }
+    }
+    // factored panel back to Mx
+#pragma clang loop unroll(disable)
+    for (int idx = t; idx < nrow * WNB; idx += WG) Mx[(size_t)(p0 + idx / WNB) * NP + p0 + (idx % WNB)] = w.Pn[idx];
+    __syncthreads();
+    // trailing update: rows and columns >= p0 + 16, 4 x 4 blocks per thread
+    const int m0 = p0 + WNB, mt = NP - m0;
+    if (mt > 0) {
+      const int nb = mt / 4;
+#pragma clang loop unroll(disable)
+      for (int bidx = t; bidx < nb * nb; bidx += WG) {
+        const int bi = bidx / nb, bj = bidx - bi * nb;
+        const int i0 = m0 + 4 * bi, j0 = m0 + 4 * bj;
+        double a[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) a[r][c] = Mx[(size_t)(i0 + r) * NP + j0 + c];
+#pragma unroll
+        for (int q = 0; q < WNB; ++q) {
+          double lq[4], uq[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) lq[r] = w.Pn[(i0 + r - p0) * WNB + q];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) uq[c] = w.Ub[q * NP + j0 + c];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) a[r][c] = fma(-lq[r], uq[c], a[r][c]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) Mx[(size_t)(i0 + r) * NP + j0 + c] = a[r][c];
+      }
+    }
+    __syncthreads();
+  }
+  // composition of the interchanges: row i of P M is row perm[i] of M
+  if (t == 0) {
+    for (int i = 0; i < NP; ++i) w.perm[i] = i;
+    for (int k = 0; k < NP; ++k) {
+      const int pr = w.piv[k];
+      const int a = w.perm[k];
+      w.perm[k] = w.perm[pr];
+      w.perm[pr] = a;
+    }
+  }
+  __syncthreads();
+  const int info = w.flag[2];
+  __syncthreads();
+  return info;
+}
+
+// Solve M x = b with the factors in Mx; thread t holds b_t and gets x_t.
+__device__ inline double wg_solve(const WgWs& w, const double* Mx, int NP, double b) {
+  const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+  if (t < NP) w.vec[t] = b;
+  __syncthreads();
+  double v = t < NP ? w.vec[w.perm[t]] : 0.0;
+  __syncthreads();
+  if (t < NP) w.vec[t] = v;
+  __syncthreads();
+  // forward substitution with unit-lower L, 16 rows per block
+#pragma clang loop unroll(disable)
+  for (int p0 = 0; p0 < NP; p0 += WNB) {
+    if (wv == 0) {
+      double y = lane < WNB ? w.vec[p0 + lane] : 0.0;
+      double Lr[WNB];
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) Lr[c] = lane < WNB ? Mx[(size_t)(p0 + lane) * NP + p0 + c] : 0.0;
+#pragma unroll
+      for (int c = 0; c < WNB - 1; ++c) {
+        const double yc = readlane(y, c);
+        y = lane > c ? fma(-Lr[c], yc, y) : y;
+      }
+      if (lane < WNB) w.vec[p0 + lane] = y;
+    }
+    __syncthreads();
+    const int i = p0 + WNB + t;
+    if (i < NP) {
+      double s = w.vec[i];
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) s = fma(-Mx[(size_t)i * NP + p0 + c], w.vec[p0 + c], s);
+      w.vec[i] = s;
+    }
+    __syncthreads();
+  }
+  // back substitution with U, last block first
+#pragma clang loop unroll(disable)
+  for (int p0 = NP - WNB; p0 >= 0; p0 -= WNB) {
+    if (wv == 0) {
+      double y = lane < WNB ? w.vec[p0 + lane] : 0.0;
+      const double rd = lane < WNB ? w.rdg[p0 + lane] : 0.0;
+      double Ur[WNB];
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) Ur[c] = lane < WNB ? Mx[(size_t)(p0 + lane) * NP + p0 + c] : 0.0;
+#pragma unroll
+      for (int c = WNB - 1; c >= 0; --c) {
+        const double xc = readlane(y * rd, c);
+        y = lane < c ? fma(-Ur[c], xc, y) : y;
+      }
+      if (lane < WNB) w.vec[p0 + lane] = y * rd;
+    }
+    __syncthreads();
+    if (t < p0) {
+      double s = w.vec[t];
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) s = fma(-Mx[(size_t)t * NP + p0 + c], w.vec[p0 + c], s);
+      w.vec[t] = s;
+    }
+    __syncthreads();
+  }
+  const double x = t < NP ? w.vec[t] : 0.0;
+  __syncthreads();
+  return x;
+}
+
+}  // namespace chem
+
+namespace chem {
+
+// One Rosenbrock attempt of the workgroup path (the same stage recurrence as
+// the wavefront path).  Returns 0, 1 (singular M) or 2 (non-finite M).
+__device__ inline int wg_attempt(const MechView& m, const WgWs& w, const double* Sx, double* Mx, int NP,
+                                 const RosTable& tab, double p, double y, double f0, double h, double& ynew,
+                                 double& err) {
+  const int N = m.d.N, t = threadIdx.x;
+  if (!wg_form(m, w, Sx, Mx, NP, 1.0 / (tab.gamma * h))) return 2;
+  if (wg_lu(w, Mx, NP)) return 1;
+  const double ih = 1.0 / h;
+  const int s = tab.s;
+  double K0 = 0.0, K1 = 0.0, K2 = 0.0, K3 = 0.0;
+  double fi = f0;
+#pragma clang loop unroll(disable)
+  for (int i = 0; i < s; ++i) {
+    const double a0 = i >= 1 ? tab.a[i][i - 1] : 0.0, c0 = i >= 1 ? tab.c[i][i - 1] : 0.0;
+    const double a1 = i >= 2 ? tab.a[i][i - 2] : 0.0, c1 = i >= 2 ? tab.c[i][i - 2] : 0.0;
+    const double a2 = i >= 3 ? tab.a[i][i - 3] : 0.0, c2 = i >= 3 ? tab.c[i][i - 3] : 0.0;
+    if (i > 0 && tab.newf[i]) {
+      const double Yi = y + a0 * K0 + a1 * K1 + a2 * K2;
+      fi = wg_rhs(m, w, t < N ? Yi : 0.0, p);
+    }
+    const double r = fi + ih * (c0 * K0 + c1 * K1 + c2 * K2);
+    const double ki = wg_solve(w, Mx, NP, t < N ? r : 0.0);
+    K3 = K2;
+    K2 = K1;
+    K1 = K0;
+    K0 = ki;
+  }
+  const double m0 = tab.m[s - 1], e0 = tab.e[s - 1];
+  const double m1 = s >= 2 ? tab.m[s - 2] : 0.0, e1 = s >= 2 ? tab.e[s - 2] : 0.0;
+  const double m2 = s >= 3 ? tab.m[s - 3] : 0.0, e2 = s >= 3 ? tab.e[s - 3] : 0.0;
+  const double m3 = s >= 4 ? tab.m[s - 4] : 0.0, e3 = s >= 4 ? tab.e[s - 4] : 0.0;
+  ynew = y + (m0 * K0 + m1 * K1 + m2 * K2 + m3 * K3);
+  err = e0 * K0 + e1 * K1 + e2 * K2 + e3 * K3;
+  return 0;
+}
+
+// Adaptive integration of cell c over [0, dt] by the whole workgroup, with the
+// controller of the wavefront path.  Every control value is computed
+// identically by all threads (from workgroup sums), so branches are uniform.
+__device__ inline void wg_integrate_cell(const MechView& m, const WgWs& w, const WgTerms& tl, double* Sx, double* Mx,
+                                         int NP, const IntArgs& a, int64_t c) {
+  const int t = threadIdx.x, N = m.d.N;
+  double y = t < N ? a.state[(int64_t)t * a.ld + c] : 0.0;
+  const double dt = a.dt;
+  const double hin = a.h[c];
+  double hprop = (__builtin_isfinite(hin) && hin > 0.0) ? fmin(hin, dt) : dt;
+  int status = ST_OK, steps = 0, rejects = 0, attempts = 0;
+  const bool bad = t < N && (!__builtin_isfinite(y) || (t == 0 && !(y > 0.0)));
+  if (block_any(bad, w.flag + 1)) status = ST_NONFINITE;
+  double tt = 0.0;
+  bool rej_last = false;
+  const RosTable& tab = kTables[a.method];
+  while (status == ST_OK && tt < dt) {
+    const double f0 = wg_jac(m, w, tl, Sx, NP, y, a.p);
+    bool fresh = true;
+    int nsing = 0;
+    bool accepted = false;
+    while (!accepted) {
+      if (attempts >= a.ctl.max_steps) { status = ST_TOO_MANY; break; }
+      if (!(hprop >= a.ctl.h_min)) { status = ST_UNDERFLOW; break; }
+      double h = hprop;
+      bool clipped = false;
+      if (h >= dt - tt) { h = dt - tt; clipped = true; }
+      ++attempts;
+      if (fresh && block_any(t < N && !__builtin_isfinite(f0), w.flag + 1)) { status = ST_NONFINITE; break; }
+      double ynew, err;
+      const int rc = wg_attempt(m, w, Sx, Mx, NP, tab, a.p, y, f0, h, ynew, err);
+      if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
+      fresh = false;
+      if (rc) {
+        ++rejects;
+        if (++nsing > 5) { status = ST_SINGULAR; break; }
+        hprop = 0.5 * h;
+        rej_last = true;
+        continue;
+      }
+      double e = 0.0;
+      if (t < N) {
+        const double sc = a.atol + a.rtol * fmax(fabs(y), fabs(ynew));
+        e = err / sc;
+      }
+      const double en = sqrt(block_sum(e * e, w.red) / N);
+      const bool fin = __builtin_isfinite(en) && !block_any(t < N && !__builtin_isfinite(ynew), w.flag + 1);
+      if (!fin) {
+        ++rejects;
+        hprop = a.ctl.fac_min * h;
+        rej_last = true;
+        continue;
+      }
+      const double fac = fmin(a.ctl.fac_max, fmax(a.ctl.fac_min, a.ctl.fac_safe * pow(en, -1.0 / a.q)));
+      if (en <= 1.0) {
+        accepted = true;
+        ++steps;
+        tt = clipped ? dt : tt + h;
+        y = ynew;
+        double hn = h * fac;
+        if (rej_last) hn = fmin(hn, h);
+        if (clipped) hn = fmax(hn, hprop);
+        hprop = hn;
+        rej_last = false;
+      } else {
+        ++rejects;
+        hprop = h * fac;
+        rej_last = true;
+      }
+    }
+  }
+  if (t < N) a.state[(int64_t)t * a.ld + c] = y;
+  if (t == 0) {
+    a.h[c] = fmin(hprop, dt);
+    if (a.steps) a.steps[c] = steps;
+    if (a.rejects) a.rejects[c] = rejects;
+    if (a.status) a.status[c] = status;
+  }
+  __syncthreads();
+}
+
+}  // namespace chem

@@ -35,7 +35,7 @@ def test_exports_every_declared_symbol(L):
 
 
 def test_max_n(L):
-    assert L.chem_max_n() == 64
+    assert L.chem_max_n() == 255  # wavefront path up to 64, workgroup path above
 
 
 def test_invalid_arguments_are_rejected_on_host(L):
