@@ -119,6 +119,7 @@ __global__ __launch_bounds__(256) void k_lu_solve(int64_t nmat, int n, const dou
 // ---------------------------------------------------------------- workgroup path (64 < N <= 256)
 // One cell per 256-thread workgroup; each workgroup owns a scratch slot of two
 // NP x NP matrices.  The grid is persistent (cells come from the queue).
+template <bool PROF>
 __global__ __launch_bounds__(WG) void k_integrate_wg(IntArgs a, WgTerms tl, double* scratch, int NP) {
   extern __shared__ __align__(16) uint8_t lds[];
   stage_blob(lds, a.blob, a.d.lds_bytes);
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(WG) void k_integrate_wg(IntArgs a, WgTerms tl, doub
   __syncthreads();
   while (idx < a.ncells) {
     const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
-    wg_integrate_cell(m, w, tl, Sx, Mx, NP, a, c);
+    wg_integrate_cell<PROF>(m, w, tl, Sx, Mx, NP, a, c);
     if (threadIdx.x == 0) w.flag[3] = atomicAdd(a.queue, 1);
     __syncthreads();
     idx = w.flag[3];
@@ -402,10 +403,11 @@ int launch_integrate_wg(chem_mech* m, const IntArgs& a0, hipStream_t s) {
   if ((size_t)grid * 2 * m->wg_np * m->wg_np * sizeof(double) > m->wg_scr_bytes)
     return fail(CHEM_EINVAL, "workgroup scratch not prepared");
   const size_t lds = wg_lds_bytes(m);
-  HIPCHK(hipFuncSetAttribute((const void*)k_integrate_wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  auto kern = a.prof ? k_integrate_wg<true> : k_integrate_wg<false>;
+  HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   a.queue = m->queue;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, m->queue);
-  hipLaunchKernelGGL(k_integrate_wg, dim3(grid), dim3(WG), lds, s, a, wg_terms(m), m->wg_scr, m->wg_np);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), lds, s, a, wg_terms(m), m->wg_scr, m->wg_np);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -687,6 +689,7 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
       for (int l = 0; l < K; ++l) {
         if (bycol[l].empty()) continue;
         wgrp.push_back(((uint32_t)wterm.size() << 8) | (uint32_t)l);
+        bycol[l].back() |= (1ull << 19) | ((uint64_t)(l & 0xF) << 20) | ((uint64_t)(l >> 4) << 60);
         wterm.insert(wterm.end(), bycol[l].begin(), bycol[l].end());
       }
     }

@@ -26,8 +26,10 @@ constexpr int WNB = 16;  // panel width of the blocked LU
 // loader).  Row k (species k) owns groups [gptr[k], gptr[k+1]); group g covers
 // terms [grp[g] >> 8, grp[g+1] >> 8) and column species (grp[g] & 0xFF).  A
 // term is packed as: bits 0-15 reaction, 16-18 kind (0-2 reactant slot, 3-5
-// product slot, 6 third-body efficiency), 24-31 nu (int8), 32-39 and 40-47 the
-// two other molecules of that side (K = padding), 48-59 efficiency entry.
+// product slot, 6 third-body efficiency), 19 last term of its column group,
+// 20-23 and 60-63 the group's column species (low and high nibble), 24-31 nu
+// (int8), 32-39 and 40-47 the two other molecules of that side (K =
+// padding), 48-59 efficiency entry.
 struct WgTerms {
   const int32_t* gptr;  // [K+1]
   const uint32_t* grp;  // [G+1] (sentinel at G)
@@ -55,10 +57,12 @@ struct WgWs {
   double* red;   // [16] block reduction scratch
   int* piv;      // [NP] row interchanges of the LU
   int* perm;     // [NP] their composition (row i of P M is row perm[i] of M)
-  int* flag;     // [4] flags and the queue broadcast
+  int* flag;     // [4] flags and the queue broadcast; [4] interchange count of the panel
+  int* sdst;     // [32] rows written by the panel's interchanges
+  int* ssrc;     // [32] the rows they take their values from
 };
 
-__host__ __device__ inline int wg_ws_doubles(int R, int NP) { return 4 * R + 9 * NP + 2 * WNB * NP + 16 + NP + 4; }
+__host__ __device__ inline int wg_ws_doubles(int R, int NP) { return 4 * R + 9 * NP + 2 * WNB * NP + 16 + NP + 40; }
 
 __device__ inline WgWs make_wg_ws(double* base, int R, int NP) {
   WgWs w;
@@ -81,6 +85,8 @@ __device__ inline WgWs make_wg_ws(double* base, int R, int NP) {
   w.piv = (int*)(w.red + 16);
   w.perm = w.piv + NP;
   w.flag = w.perm + NP;
+  w.sdst = w.flag + 8;
+  w.ssrc = w.sdst + 32;
   return w;
 }
 
@@ -263,16 +269,20 @@ __device__ inline double wg_jac(const MechView& m, const WgWs& w, const WgTerms&
     }
     // structural nonzeros of row k, one group per column, terms in a fixed order
     double* Srow = Sx + (size_t)t * NP + 1;
-    const int g1 = tl.gptr[k + 1];
+    const int g0 = tl.gptr[k], g1 = tl.gptr[k + 1];
+    // the row's terms are contiguous; eight term words are loaded per pass and
+    // the last term of each column group carries the column and closes it
+    const int tb = (int)(tl.grp[g0] >> 8), te = (int)(tl.grp[g1] >> 8);
+    double acc = 0.0;
 #pragma clang loop unroll(disable)
-    for (int gi = tl.gptr[k]; gi < g1; ++gi) {
-      const uint32_t gw = tl.grp[gi];
-      const int col = (int)(gw & 0xFF);
-      const int t1 = (int)(tl.grp[gi + 1] >> 8);
-      double acc = 0.0;
-#pragma clang loop unroll(disable)
-      for (int ti = (int)(gw >> 8); ti < t1; ++ti) {
-        const uint64_t tw = tl.term[ti];
+    for (int ti = tb; ti < te; ti += 8) {
+      uint64_t tw8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) tw8[u] = ti + u < te ? tl.term[ti + u] : 0ull;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (ti + u >= te) break;
+        const uint64_t tw = tw8[u];
         const int r = (int)(tw & 0xFFFF);
         const int kind = (int)((tw >> 16) & 7);
         const double nu = (double)(int8_t)((tw >> 24) & 0xFF);
@@ -282,9 +292,13 @@ __device__ inline double wg_jac(const MechView& m, const WgWs& w, const WgTerms&
         else if (kind < 6) v = -w.rkr[r] * co;
         else v = w.rdm[r] * m.tbd[(tw >> 48) & 0xFFF];
         acc += nu * v;
+        if ((tw >> 19) & 1) {
+          const int col = (int)(((tw >> 20) & 0xF) | (((tw >> 60) & 0xF) << 4));
+          Srow[col] = acc;
+          sk += w.C[col] * acc;
+          acc = 0.0;
+        }
       }
-      Srow[col] = acc;
-      sk += w.C[col] * acc;
     }
   }
   // sk = sum_l C_l (S_kl + adense_k); C sums to Ctot
@@ -321,10 +335,20 @@ __device__ inline double wg_jac(const MechView& m, const WgWs& w, const WgTerms&
   // row 0 of J: column sums of the species rows weighted by mass enthalpy
   if (isSp) {
     const int l = t - 1;
-    double cs = 0.0;
     const double* Sc = Sx + NP + 1 + l;
+    const double RT = RU * x.T;
+    double ps[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int k = 0;
 #pragma clang loop unroll(disable)
-    for (int k = 0; k < K; ++k) cs += (RU * x.T * w.hR[k]) * Sc[(size_t)k * NP];
+    for (; k + 8 <= K; k += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = Sc[(size_t)(k + u) * NP];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ps[u] = fma(RT * w.hR[k + u], v[u], ps[u]);
+    }
+    for (; k < K; ++k) ps[0] = fma(RT * w.hR[k], Sc[(size_t)k * NP], ps[0]);
+    const double cs = ((ps[0] + ps[1]) + (ps[2] + ps[3])) + ((ps[4] + ps[5]) + (ps[6] + ps[7]));
     const double colsum = m.iW[l] * (cs + sA + sG);
     w.jTr[t] = -(colsum + fT * cpm) / x.cp;
   } else if (t == 0) {
@@ -337,103 +361,253 @@ __device__ inline double wg_jac(const MechView& m, const WgWs& w, const WgTerms&
 // M = I/(gamma h) - J into Mx (NP x NP, identity on the padding); returns
 // false if an entry is not finite.
 __device__ inline bool wg_form(const MechView& m, const WgWs& w, const double* Sx, double* Mx, int NP, double d) {
-  const int N = m.d.N;
+  const int N = m.d.N, tot = NP * NP;
   bool bad = false;
+  // eight elements per pass: their scratch loads are in flight together
 #pragma clang loop unroll(disable)
-  for (int idx = threadIdx.x; idx < NP * NP; idx += WG) {
-    const int i = idx / NP, j = idx - i * NP;
-    double v;
-    if (i >= N || j >= N) {
-      v = i == j ? 1.0 : 0.0;
-    } else {
-      double J;
-      if (i == 0) J = w.jTr[j];
-      else if (j == 0) J = w.jT0[i];
-      else J = m.iW[j - 1] * (m.W[i - 1] * (Sx[idx] + w.ad[i]) + w.gam[i]);
-      v = (i == j ? d : 0.0) - J;
-      bad |= !__builtin_isfinite(v);
+  for (int base = threadIdx.x; base < tot; base += 8 * WG) {
+    double sv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * WG;
+      sv[u] = idx < tot ? Sx[idx] : 0.0;
     }
-    Mx[idx] = v;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int idx = base + u * WG;
+      if (idx >= tot) break;
+      const int i = idx / NP, j = idx - i * NP;
+      double v;
+      if (i >= N || j >= N) {
+        v = i == j ? 1.0 : 0.0;
+      } else {
+        double J;
+        if (i == 0) J = w.jTr[j];
+        else if (j == 0) J = w.jT0[i];
+        else J = m.iW[j - 1] * (m.W[i - 1] * (sv[u] + w.ad[i]) + w.gam[i]);
+        v = (i == j ? d : 0.0) - J;
+        bad |= !__builtin_isfinite(v);
+      }
+      Mx[idx] = v;
+    }
   }
   return !block_any(bad, w.flag + 1);
 }
 
+// Factors the panel (rows p0..NP-1, columns p0..p0+15, staged in Pn) in the
+// registers of wave 0: relative row r sits in lane r % 64, slot r / 64.  The
+// pivot is the first row with the largest |a| (exact comparison of the
+// non-negative doubles as integers, then the smallest row index); the pivot
+// row is broadcast with readlane and swapped into row kk.  Records piv, 1/U_kk
+// and a zero-pivot step in flag[2]; leaves the factored panel in Pn.
+template <int NS>
+__device__ inline void wg_panel(const WgWs& w, int p0, int NP, int lane) {
+  const int nrow = NP - p0;
+  double P[NS][WNB];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int rel = sl * WAVE + lane;
+#pragma unroll
+    for (int c = 0; c < WNB; ++c) P[sl][c] = rel < nrow ? w.Pn[rel * WNB + c] : 0.0;
+  }
+#pragma clang loop unroll(full)
+  for (int kk = 0; kk < WNB; ++kk) {
+    double best = -1.0;
+    int brel = 1 << 20;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int rel = sl * WAVE + lane;
+      const double v = fabs(P[sl][kk]);
+      if (rel >= kk && rel < nrow && v > best) {
+        best = v;
+        brel = rel;
+      }
+    }
+    const unsigned long long key = __builtin_bit_cast(unsigned long long, best < 0.0 ? 0.0 : best);
+    const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
+    const unsigned mh = wave_max_u32(best < 0.0 ? 0u : hi);
+    const unsigned ml = wave_max_u32((best >= 0.0 && hi == mh) ? lo : 0u);
+    int cand = (best >= 0.0 && hi == mh && lo == ml) ? brel : (1 << 20);
+    cand = min(cand, __shfl_xor(cand, 32));
+    cand = min(cand, __shfl_xor(cand, 16));
+    cand = min(cand, __shfl_xor(cand, 8));
+    cand = min(cand, __shfl_xor(cand, 4));
+    cand = min(cand, __shfl_xor(cand, 2));
+    cand = min(cand, __shfl_xor(cand, 1));
+    int pr = uniform_int(cand);
+    pr = pr < nrow ? pr : kk;
+    const int lp = pr & (WAVE - 1), sp = pr / WAVE;
+    double b[WNB];
+#pragma unroll
+    for (int c = 0; c < WNB; ++c) {
+      double x = P[0][c];
+#pragma unroll
+      for (int sl = 1; sl < NS; ++sl) x = sp == sl ? P[sl][c] : x;
+      b[c] = readlane(x, lp);
+    }
+    const double pv = b[kk];
+    const bool sing = !(pv != 0.0);
+    if (!sing && pr != kk) {
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) {
+        const double a = readlane(P[0][c], kk);
+#pragma unroll
+        for (int sl = 0; sl < NS; ++sl) P[sl][c] = (lane == lp && sp == sl) ? a : P[sl][c];
+        P[0][c] = lane == kk ? b[c] : P[0][c];
+      }
+    }
+    const double rp = sing ? 0.0 : 1.0 / pv;
+    if (lane == 0) {
+      w.piv[p0 + kk] = (sing ? kk : pr) + p0;
+      w.rdg[p0 + kk] = rp;
+      if (sing && w.flag[2] == 0) w.flag[2] = p0 + kk + 1;
+    }
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int rel = sl * WAVE + lane;
+      if (rel > kk && rel < nrow) {
+        const double l = P[sl][kk] * rp;
+        P[sl][kk] = l;
+#pragma clang loop unroll(full)
+        for (int c = kk + 1; c < WNB; ++c) P[sl][c] = fma(-l, b[c], P[sl][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int rel = sl * WAVE + lane;
+    if (rel < nrow) {
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) w.Pn[rel * WNB + c] = P[sl][c];
+    }
+  }
+  wsync();
+}
+
+// Panel factorization in LDS by wave 0 (any panel height; used above 192 rows,
+// where the register version would not fit).  Same pivot rule and records.
+__device__ inline void wg_panel_lds(const WgWs& w, int p0, int NP, int lane) {
+#pragma clang loop unroll(disable)
+  for (int kk = 0; kk < WNB; ++kk) {
+    const int k = p0 + kk;
+    double best = -1.0;
+    int bi = NP;
+    for (int i = k + lane; i < NP; i += WAVE) {
+      const double v = fabs(w.Pn[(i - p0) * WNB + kk]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    const unsigned long long key = __builtin_bit_cast(unsigned long long, best < 0.0 ? 0.0 : best);
+    const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
+    const unsigned mh = wave_max_u32(best < 0.0 ? 0u : hi);
+    const unsigned ml = wave_max_u32((best >= 0.0 && hi == mh) ? lo : 0u);
+    int cand = (best >= 0.0 && hi == mh && lo == ml) ? bi : NP;
+    for (int o = 32; o >= 1; o >>= 1) cand = min(cand, __shfl_xor(cand, o));
+    const int pr = uniform_int(cand);
+    const double pv = (pr < NP) ? w.Pn[(pr - p0) * WNB + kk] : 0.0;
+    const bool sing = !(pv != 0.0);
+    if (lane == 0) {
+      w.piv[k] = sing ? k : pr;
+      if (sing && w.flag[2] == 0) w.flag[2] = k + 1;
+    }
+    const int prow = sing ? k : pr;
+    if (lane < WNB && prow != k) {
+      const double a = w.Pn[(k - p0) * WNB + lane], b = w.Pn[(prow - p0) * WNB + lane];
+      w.Pn[(k - p0) * WNB + lane] = b;
+      w.Pn[(prow - p0) * WNB + lane] = a;
+    }
+    wsync();
+    const double rp = sing ? 0.0 : 1.0 / pv;
+    if (lane == 0) w.rdg[k] = rp;
+    for (int i = k + 1 + lane; i < NP; i += WAVE) {
+      double* Pr = w.Pn + (i - p0) * WNB;
+      const double l = Pr[kk] * rp;
+      Pr[kk] = l;
+      for (int c = kk + 1; c < WNB; ++c) Pr[c] = fma(-l, w.Pn[(k - p0) * WNB + c], Pr[c]);
+    }
+    wsync();
+  }
+}
+
 // Blocked LU with partial pivoting of Mx in place.  Returns the 1-based step
 // of a zero pivot column, or 0.  Leaves piv, perm and 1/U_kk in LDS.
-__device__ inline int wg_lu(const WgWs& w, double* Mx, int NP) {
+template <bool PROF = false>
+__device__ inline int wg_lu(const WgWs& w, double* Mx, int NP, Prof<PROF>* pf = nullptr) {
   const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+  unsigned long long tp = 0;
   if (t == 0) w.flag[2] = 0;
 #pragma clang loop unroll(disable)
   for (int p0 = 0; p0 < NP; p0 += WNB) {
     const int nrow = NP - p0;
     // panel to LDS
-#pragma clang loop unroll(disable)
-    for (int idx = t; idx < nrow * WNB; idx += WG) w.Pn[idx] = Mx[(size_t)(p0 + idx / WNB) * NP + p0 + (idx % WNB)];
-    __syncthreads();
-    if (wv == 0) {
-#pragma clang loop unroll(disable)
-      for (int kk = 0; kk < WNB; ++kk) {
-        const int k = p0 + kk;
-        // first row with the largest |a| in column kk among rows >= k
-        double best = -1.0;
-        int bi = NP;
-        for (int i = k + lane; i < NP; i += WAVE) {
-          const double v = fabs(w.Pn[(i - p0) * WNB + kk]);
-          if (v > best) {
-            best = v;
-            bi = i;
-          }
-        }
-        unsigned long long key = __builtin_bit_cast(unsigned long long, best < 0.0 ? 0.0 : best);
-        unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
-        // wave max of the 64-bit key (non-negative doubles order as integers)
-        unsigned mh = wave_max_u32(hi);
-        unsigned ml = wave_max_u32(hi == mh ? lo : 0u);
-        const bool mine = hi == mh && lo == ml && best >= 0.0;
-        int cand = mine ? bi : NP;
-        // smallest row index among the lanes holding the maximum
-        for (int o = 32; o >= 1; o >>= 1) cand = min(cand, __shfl_xor(cand, o));
-        const int pr = uniform_int(cand);
-        const double pv = (pr < NP) ? w.Pn[(pr - p0) * WNB + kk] : 0.0;
-        const bool sing = !(pv != 0.0);
-        if (lane == 0) {
-          w.piv[k] = sing ? k : pr;
-          if (sing && w.flag[2] == 0) w.flag[2] = k + 1;
-        }
-        const int prow = sing ? k : pr;
-        // swap rows k and prow of the panel
-        if (lane < WNB && prow != k) {
-          const double a = w.Pn[(k - p0) * WNB + lane], b = w.Pn[(prow - p0) * WNB + lane];
-          w.Pn[(k - p0) * WNB + lane] = b;
-          w.Pn[(prow - p0) * WNB + lane] = a;
-        }
-        wsync();
-        const double rp = sing ? 0.0 : 1.0 / pv;
-        if (lane == 0) w.rdg[k] = rp;
-        // multipliers and the rank-1 update of the panel's remaining columns
-        for (int i = k + 1 + lane; i < NP; i += WAVE) {
-          double* Pr = w.Pn + (i - p0) * WNB;
-          const double l = Pr[kk] * rp;
-          Pr[kk] = l;
-          for (int c = kk + 1; c < WNB; ++c) Pr[c] = fma(-l, w.Pn[(k - p0) * WNB + c], Pr[c]);
-        }
-        wsync();
+    {
+      double pv[WNB];
+#pragma unroll
+      for (int u = 0; u < WNB; ++u) {
+        const int idx = t + u * WG;
+        pv[u] = idx < nrow * WNB ? Mx[(size_t)(p0 + idx / WNB) * NP + p0 + (idx % WNB)] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < WNB; ++u) {
+        const int idx = t + u * WG;
+        if (idx < nrow * WNB) w.Pn[idx] = pv[u];
       }
     }
     __syncthreads();
-    // row interchanges on the columns outside the panel (each thread owns
-    // whole columns, so the sequence of swaps stays ordered per column)
+    if (PROF) tp = pf->now();
+    if (wv == 0) {
+      if (nrow <= 3 * WAVE) wg_panel<3>(w, p0, NP, lane);
+      else wg_panel_lds(w, p0, NP, lane);
+      // the panel's 16 interchanges composed on the rows they touch (at most
+      // 32, one per lane): afterwards row sdst[i] holds old row ssrc[i]
+      int myrow = -1, mysrc = -1, nt = 0;
+#pragma clang loop unroll(disable)
+      for (int kk = 0; kk < WNB; ++kk) {
+        const int k = p0 + kk, q = w.piv[k];
+        if (q == k) continue;
+        const unsigned long long bk = ballot(myrow == k);
+        int sk = nt;
+        if (bk) sk = (int)__builtin_ctzll(bk);
+        else {
+          if (lane == nt) myrow = mysrc = k;
+          ++nt;
+        }
+        const unsigned long long bq = ballot(myrow == q);
+        int sq = nt;
+        if (bq) sq = (int)__builtin_ctzll(bq);
+        else {
+          if (lane == nt) myrow = mysrc = q;
+          ++nt;
+        }
+        const int srck = __builtin_amdgcn_readlane(mysrc, sk), srcq = __builtin_amdgcn_readlane(mysrc, sq);
+        if (lane == sk) mysrc = srcq;
+        if (lane == sq) mysrc = srck;
+      }
+      if (lane < nt) {
+        w.sdst[lane] = myrow;
+        w.ssrc[lane] = mysrc;
+      }
+      if (lane == 0) w.flag[4] = nt;
+    }
+    __syncthreads();
+    if (PROF) {
+      pf->add(6, tp);
+      tp = pf->now();
+    }
+    // row interchanges on the columns outside the panel: each thread owns a
+    // column, loads every source row first, then stores
+    const int nsw = w.flag[4];
 #pragma clang loop unroll(disable)
     for (int j = t; j < NP; j += WG) {
       if (j >= p0 && j < p0 + WNB) continue;
-      for (int kk = 0; kk < WNB; ++kk) {
-        const int k = p0 + kk, pr = w.piv[k];
-        if (pr != k) {
-          const double a = Mx[(size_t)k * NP + j], b = Mx[(size_t)pr * NP + j];
-          Mx[(size_t)k * NP + j] = b;
-          Mx[(size_t)pr * NP + j] = a;
-        }
-      }
+      double v[2 * WNB];
+#pragma unroll
+      for (int i = 0; i < 2 * WNB; ++i) v[i] = i < nsw ? Mx[(size_t)w.ssrc[i] * NP + j] : 0.0;
+#pragma unroll
+      for (int i = 0; i < 2 * WNB; ++i)
+        if (i < nsw) Mx[(size_t)w.sdst[i] * NP + j] = v[i];
       // rows of U of this panel: U12 = L11^-1 A12 (column j, forward substitution)
       if (j >= p0 + WNB) {
         double u[WNB];
@@ -455,35 +629,53 @@ __device__ inline int wg_lu(const WgWs& w, double* Mx, int NP) {
 #pragma clang loop unroll(disable)
     for (int idx = t; idx < nrow * WNB; idx += WG) Mx[(size_t)(p0 + idx / WNB) * NP + p0 + (idx % WNB)] = w.Pn[idx];
     __syncthreads();
+    if (PROF) pf->add(7, tp);
     // trailing update: rows and columns >= p0 + 16, 4 x 4 blocks per thread
     const int m0 = p0 + WNB, mt = NP - m0;
     if (mt > 0) {
       const int nb = mt / 4;
+      // two blocks per pass so that 32 loads are in flight together
 #pragma clang loop unroll(disable)
-      for (int bidx = t; bidx < nb * nb; bidx += WG) {
-        const int bi = bidx / nb, bj = bidx - bi * nb;
-        const int i0 = m0 + 4 * bi, j0 = m0 + 4 * bj;
-        double a[4][4];
+      for (int bidx = t; bidx < nb * nb; bidx += 2 * WG) {
+        const bool two = bidx + WG < nb * nb;
+        int i0[2], j0[2];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int u = 0; u < 2; ++u) {
+          const int bb = (u == 0 || two) ? bidx + u * WG : bidx;
+          const int bi = bb / nb;
+          i0[u] = m0 + 4 * bi;
+          j0[u] = m0 + 4 * (bb - bi * nb);
+        }
+        double a[2][4][4];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) a[r][c] = Mx[(size_t)(i0 + r) * NP + j0 + c];
-#pragma unroll
-        for (int q = 0; q < WNB; ++q) {
-          double lq[4], uq[4];
-#pragma unroll
-          for (int r = 0; r < 4; ++r) lq[r] = w.Pn[(i0 + r - p0) * WNB + q];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) uq[c] = w.Ub[q * NP + j0 + c];
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
           for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) a[r][c] = fma(-lq[r], uq[c], a[r][c]);
+            for (int c = 0; c < 4; ++c) a[u][r][c] = Mx[(size_t)(i0[u] + r) * NP + j0[u] + c];
+#pragma unroll
+        for (int q = 0; q < WNB; ++q) {
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            double lq[4], uq[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lq[r] = w.Pn[(i0[u] + r - p0) * WNB + q];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) uq[c] = w.Ub[q * NP + j0[u] + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int c = 0; c < 4; ++c) a[u][r][c] = fma(-lq[r], uq[c], a[u][r][c]);
+          }
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
+        for (int u = 0; u < 2; ++u) {
+          if (u == 1 && !two) break;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) Mx[(size_t)(i0 + r) * NP + j0 + c] = a[r][c];
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) Mx[(size_t)(i0[u] + r) * NP + j0[u] + c] = a[u][r][c];
+        }
       }
     }
     __syncthreads();
@@ -505,67 +697,84 @@ __device__ inline int wg_lu(const WgWs& w, double* Mx, int NP) {
 }
 
 // Solve M x = b with the factors in Mx; thread t holds b_t and gets x_t.
+// Thread t also owns row t of the factors: at each 16-column block it holds
+// that block's 16 entries of its row in registers and has the next block's
+// entries in flight, so the global-memory latency is paid once per solve.  The
+// 16 x 16 diagonal block is solved by the wave that owns its rows (rows
+// p0..p0+15 are 16 consecutive lanes of one wave).
 __device__ inline double wg_solve(const WgWs& w, const double* Mx, int NP, double b) {
-  const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+  const int t = threadIdx.x, wv = t / WAVE;
+  const double* Mrow = Mx + (size_t)(t < NP ? t : 0) * NP;
+  double seg[WNB], nxt[WNB];
+  // first forward block (columns 0..15) in flight while b is permuted
+#pragma unroll
+  for (int c = 0; c < WNB; ++c) nxt[c] = t < NP ? Mrow[c] : 0.0;
   if (t < NP) w.vec[t] = b;
   __syncthreads();
-  double v = t < NP ? w.vec[w.perm[t]] : 0.0;
+  double y = t < NP ? w.vec[w.perm[t]] : 0.0;
   __syncthreads();
-  if (t < NP) w.vec[t] = v;
-  __syncthreads();
-  // forward substitution with unit-lower L, 16 rows per block
+  // forward substitution with unit-lower L
 #pragma clang loop unroll(disable)
   for (int p0 = 0; p0 < NP; p0 += WNB) {
-    if (wv == 0) {
-      double y = lane < WNB ? w.vec[p0 + lane] : 0.0;
-      double Lr[WNB];
 #pragma unroll
-      for (int c = 0; c < WNB; ++c) Lr[c] = lane < WNB ? Mx[(size_t)(p0 + lane) * NP + p0 + c] : 0.0;
+    for (int c = 0; c < WNB; ++c) seg[c] = nxt[c];
+    const int pn = p0 + WNB;
+    if (pn < NP && t >= pn) {
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) nxt[c] = Mrow[pn + c];
+    }
+    if (wv == p0 / WAVE) {  // diagonal block: lanes l0 .. l0+15 of this wave
+      const int l0 = p0 & (WAVE - 1);
+      const bool inb = t >= p0 && t < pn;
 #pragma unroll
       for (int c = 0; c < WNB - 1; ++c) {
-        const double yc = readlane(y, c);
-        y = lane > c ? fma(-Lr[c], yc, y) : y;
+        const double yc = readlane(y, l0 + c);
+        y = (inb && t > p0 + c) ? fma(-seg[c], yc, y) : y;
       }
-      if (lane < WNB) w.vec[p0 + lane] = y;
+      if (inb) w.vec[t] = y;
     }
     __syncthreads();
-    const int i = p0 + WNB + t;
-    if (i < NP) {
-      double s = w.vec[i];
+    if (t >= pn && t < NP) {
 #pragma unroll
-      for (int c = 0; c < WNB; ++c) s = fma(-Mx[(size_t)i * NP + p0 + c], w.vec[p0 + c], s);
-      w.vec[i] = s;
+      for (int c = 0; c < WNB; ++c) y = fma(-seg[c], w.vec[p0 + c], y);
     }
     __syncthreads();
   }
   // back substitution with U, last block first
-#pragma clang loop unroll(disable)
-  for (int p0 = NP - WNB; p0 >= 0; p0 -= WNB) {
-    if (wv == 0) {
-      double y = lane < WNB ? w.vec[p0 + lane] : 0.0;
-      const double rd = lane < WNB ? w.rdg[p0 + lane] : 0.0;
-      double Ur[WNB];
+  const int last = NP - WNB;
 #pragma unroll
-      for (int c = 0; c < WNB; ++c) Ur[c] = lane < WNB ? Mx[(size_t)(p0 + lane) * NP + p0 + c] : 0.0;
+  for (int c = 0; c < WNB; ++c) nxt[c] = t < NP ? Mrow[last + c] : 0.0;
+#pragma clang loop unroll(disable)
+  for (int p0 = last; p0 >= 0; p0 -= WNB) {
+#pragma unroll
+    for (int c = 0; c < WNB; ++c) seg[c] = nxt[c];
+    const int pp = p0 - WNB;
+    if (pp >= 0 && t < p0) {
+#pragma unroll
+      for (int c = 0; c < WNB; ++c) nxt[c] = Mrow[pp + c];
+    }
+    if (wv == p0 / WAVE) {
+      const int l0 = p0 & (WAVE - 1);
+      const bool inb = t >= p0 && t < p0 + WNB;
+      const double rd = inb ? w.rdg[t] : 0.0;
 #pragma unroll
       for (int c = WNB - 1; c >= 0; --c) {
-        const double xc = readlane(y * rd, c);
-        y = lane < c ? fma(-Ur[c], xc, y) : y;
+        const double xc = readlane(y * rd, l0 + c);
+        y = (inb && t < p0 + c) ? fma(-seg[c], xc, y) : y;
       }
-      if (lane < WNB) w.vec[p0 + lane] = y * rd;
+      if (inb) {
+        y *= rd;
+        w.vec[t] = y;
+      }
     }
     __syncthreads();
     if (t < p0) {
-      double s = w.vec[t];
 #pragma unroll
-      for (int c = 0; c < WNB; ++c) s = fma(-Mx[(size_t)t * NP + p0 + c], w.vec[p0 + c], s);
-      w.vec[t] = s;
+      for (int c = 0; c < WNB; ++c) y = fma(-seg[c], w.vec[p0 + c], y);
     }
     __syncthreads();
   }
-  const double x = t < NP ? w.vec[t] : 0.0;
-  __syncthreads();
-  return x;
+  return t < NP ? y : 0.0;
 }
 
 }  // namespace chem
@@ -574,12 +783,18 @@ namespace chem {
 
 // One Rosenbrock attempt of the workgroup path (the same stage recurrence as
 // the wavefront path).  Returns 0, 1 (singular M) or 2 (non-finite M).
+template <bool PROF>
 __device__ inline int wg_attempt(const MechView& m, const WgWs& w, const double* Sx, double* Mx, int NP,
                                  const RosTable& tab, double p, double y, double f0, double h, double& ynew,
-                                 double& err) {
+                                 double& err, Prof<PROF>& pf) {
   const int N = m.d.N, t = threadIdx.x;
-  if (!wg_form(m, w, Sx, Mx, NP, 1.0 / (tab.gamma * h))) return 2;
-  if (wg_lu(w, Mx, NP)) return 1;
+  pf.start();
+  const bool okm = wg_form(m, w, Sx, Mx, NP, 1.0 / (tab.gamma * h));
+  pf.stop(1);
+  if (!okm) return 2;
+  const int info = wg_lu<PROF>(w, Mx, NP, &pf);
+  pf.stop(2);
+  if (info) return 1;
   const double ih = 1.0 / h;
   const int s = tab.s;
   double K0 = 0.0, K1 = 0.0, K2 = 0.0, K3 = 0.0;
@@ -591,10 +806,14 @@ __device__ inline int wg_attempt(const MechView& m, const WgWs& w, const double*
     const double a2 = i >= 3 ? tab.a[i][i - 3] : 0.0, c2 = i >= 3 ? tab.c[i][i - 3] : 0.0;
     if (i > 0 && tab.newf[i]) {
       const double Yi = y + a0 * K0 + a1 * K1 + a2 * K2;
+      pf.start();
       fi = wg_rhs(m, w, t < N ? Yi : 0.0, p);
+      pf.stop(3);
     }
     const double r = fi + ih * (c0 * K0 + c1 * K1 + c2 * K2);
+    pf.start();
     const double ki = wg_solve(w, Mx, NP, t < N ? r : 0.0);
+    pf.stop(4);
     K3 = K2;
     K2 = K1;
     K1 = K0;
@@ -612,9 +831,12 @@ __device__ inline int wg_attempt(const MechView& m, const WgWs& w, const double*
 // Adaptive integration of cell c over [0, dt] by the whole workgroup, with the
 // controller of the wavefront path.  Every control value is computed
 // identically by all threads (from workgroup sums), so branches are uniform.
+template <bool PROF>
 __device__ inline void wg_integrate_cell(const MechView& m, const WgWs& w, const WgTerms& tl, double* Sx, double* Mx,
                                          int NP, const IntArgs& a, int64_t c) {
   const int t = threadIdx.x, N = m.d.N;
+  Prof<PROF> pf;
+  const unsigned long long t_begin = PROF ? __builtin_readcyclecounter() : 0ull;
   double y = t < N ? a.state[(int64_t)t * a.ld + c] : 0.0;
   const double dt = a.dt;
   const double hin = a.h[c];
@@ -626,7 +848,9 @@ __device__ inline void wg_integrate_cell(const MechView& m, const WgWs& w, const
   bool rej_last = false;
   const RosTable& tab = kTables[a.method];
   while (status == ST_OK && tt < dt) {
+    pf.start();
     const double f0 = wg_jac(m, w, tl, Sx, NP, y, a.p);
+    pf.stop(0);
     bool fresh = true;
     int nsing = 0;
     bool accepted = false;
@@ -639,7 +863,7 @@ __device__ inline void wg_integrate_cell(const MechView& m, const WgWs& w, const
       ++attempts;
       if (fresh && block_any(t < N && !__builtin_isfinite(f0), w.flag + 1)) { status = ST_NONFINITE; break; }
       double ynew, err;
-      const int rc = wg_attempt(m, w, Sx, Mx, NP, tab, a.p, y, f0, h, ynew, err);
+      const int rc = wg_attempt<PROF>(m, w, Sx, Mx, NP, tab, a.p, y, f0, h, ynew, err, pf);
       if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
       fresh = false;
       if (rc) {
@@ -686,6 +910,14 @@ __device__ inline void wg_integrate_cell(const MechView& m, const WgWs& w, const
     if (a.steps) a.steps[c] = steps;
     if (a.rejects) a.rejects[c] = rejects;
     if (a.status) a.status[c] = status;
+  }
+  if (PROF && t < 8) {
+    unsigned long long v = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (t == i) v = pf.c[i];
+    if (t == 5) v = __builtin_readcyclecounter() - t_begin;
+    a.prof[c * 8 + t] = v;
   }
   __syncthreads();
 }
