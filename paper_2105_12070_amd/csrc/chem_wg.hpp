@@ -62,7 +62,12 @@ struct WgWs {
   int* ssrc;     // [32] the rows they take their values from
 };
 
-__host__ __device__ inline int wg_ws_doubles(int R, int NP) { return 4 * R + 9 * NP + 2 * WNB * NP + 16 + NP + 40; }
+// The Jacobian's rate arrays rkr, rdm, rdt and the LU's panel buffers Pn, Ub
+// are never live at the same time, so they share one region.
+__host__ __device__ inline int wg_ws_doubles(int R, int NP) {
+  const int shared = 2 * WNB * NP > 3 * R ? 2 * WNB * NP : 3 * R;
+  return 3 * NP + R + 5 * NP + shared + NP + 16 + NP / 2 + NP / 2 + 40;
+}
 
 __device__ inline WgWs make_wg_ws(double* base, int R, int NP) {
   WgWs w;
@@ -70,17 +75,19 @@ __device__ inline WgWs make_wg_ws(double* base, int R, int NP) {
   w.g = w.C + NP;
   w.hR = w.g + NP;
   w.rk = w.hR + NP;
-  w.rkr = w.rk + R;
-  w.rdm = w.rkr + R;
-  w.rdt = w.rdm + R;
-  w.vec = w.rdt + R;
+  w.vec = w.rk + R;
   w.ad = w.vec + NP;
   w.gam = w.ad + NP;
   w.jT0 = w.gam + NP;
   w.jTr = w.jT0 + NP;
-  w.Pn = w.jTr + NP;
+  double* shared = w.jTr + NP;
+  w.Pn = shared;
   w.Ub = w.Pn + NP * WNB;
-  w.rdg = w.Ub + NP * WNB;
+  w.rkr = shared;
+  w.rdm = w.rkr + R;
+  w.rdt = w.rdm + R;
+  const int sh = 2 * WNB * NP > 3 * R ? 2 * WNB * NP : 3 * R;
+  w.rdg = shared + sh;
   w.red = w.rdg + NP;
   w.piv = (int*)(w.red + 16);
   w.perm = w.piv + NP;
