@@ -106,6 +106,8 @@ struct OracleOpts {
   int32_t method;     // 0 ROS4, 1 Rodas3, 2 linearly implicit Euler (Eq. 2)
   int32_t max_steps;  // attempts per cell before TOO_MANY_STEPS
   double fac_safe, fac_min, fac_max, h_min;
+  int32_t jac_mode;   // 0 analytic Jacobian, 1 one-sided finite differences (section 2.3's "Standard" case)
+  int32_t lu_pivot;   // 0 partial pivoting (LAPACK), 1 no pivoting (a naive LU)
 };
 }
 
@@ -379,11 +381,12 @@ void jac_analytic(const OracleMech& m, const Params<S>& P, double p, const S* y,
 // ----------------------------------------------------------------- dense LU
 // Right-looking LU with partial pivoting (first index of max |a|), row
 // interchanges recorded in piv, unit-lower L stored below the diagonal.
-template <class S> int lu_factor(S* A, int n, int* piv) {
+// With pivot = false the rows are taken in their natural order (no search).
+template <class S> int lu_factor(S* A, int n, int* piv, bool pivot = true) {
   for (int k = 0; k < n; ++k) {
     int p = k;
     double amax = std::fabs(val(A[(size_t)k * n + k]));
-    for (int i = k + 1; i < n; ++i) {
+    for (int i = k + 1; pivot && i < n; ++i) {
       double a = std::fabs(val(A[(size_t)i * n + k]));
       if (a > amax) { amax = a; p = i; }
     }
@@ -521,12 +524,12 @@ int stage_source(const Table& t, int i) {
 // Returns 0, or 1 if M is singular.
 template <class S, class Rhs>
 int ros_step(const Table& t, int N, Rhs&& frhs, const S* y, const S* f0, const S* J, double h, S* ynew,
-             S* err) {
+             S* err, bool pivot = true) {
   std::vector<S> M((size_t)N * N), K((size_t)4 * N), fst((size_t)4 * N), Y(N), rhsv(N);
   std::vector<int> piv(N);
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) M[(size_t)i * N + j] = (i == j ? S(1.0 / (t.gamma * h)) : S(0.0)) - J[(size_t)i * N + j];
-  if (lu_factor(M.data(), N, piv.data())) return 1;
+  if (lu_factor(M.data(), N, piv.data(), pivot)) return 1;
   for (int i = 0; i < t.s; ++i) {
     S* fi = &fst[(size_t)i * N];
     if (i == 0) {
@@ -569,6 +572,23 @@ struct CellResult {
   int status, steps, rejects;
 };
 
+// One-sided finite-difference Jacobian, column j from f(y + d_j e_j):
+// d_j = sqrt(eps) max(|y_j|, 1e-10), rounded so that y_j + d_j - y_j = d_j.
+constexpr double FD_REL = 1.4901161193847656e-08, FD_FLOOR = 1e-10;
+void jac_fd(const OracleMech& m, const Params<double>& P, double p, const double* y, double* J, double* f0) {
+  const int N = m.K + 1;
+  rhs(m, P, p, y, f0);
+  std::vector<double> yp(y, y + N), fp(N);
+  for (int j = 0; j < N; ++j) {
+    double d = FD_REL * std::max(std::fabs(y[j]), FD_FLOOR);
+    d = (y[j] + d) - y[j];
+    yp[j] = y[j] + d;
+    rhs(m, P, p, yp.data(), fp.data());
+    for (int i = 0; i < N; ++i) J[(size_t)i * N + j] = (fp[i] - f0[i]) / d;
+    yp[j] = y[j];
+  }
+}
+
 // Adaptive integration of one cell over [0, dt] (controller constants in opts).
 CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol, double atol, const OracleOpts& o,
                           double* y, double* h_io, std::vector<double>* hs_out) {
@@ -588,7 +608,8 @@ CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol,
   bool rejected_last = false;
   int attempts = 0;
   while (tcur < dt) {
-    jac_analytic(m, P, p, y, J.data(), f0.data());
+    if (o.jac_mode == 1) jac_fd(m, P, p, y, J.data(), f0.data());
+    else jac_analytic(m, P, p, y, J.data(), f0.data());
     if (!all_finite(f0.data(), N) || !all_finite(J.data(), N * N)) { res.status = ST_NONFINITE; break; }
     int nsing = 0;
     bool accepted = false;
@@ -599,7 +620,7 @@ CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol,
       bool clipped = false;
       if (h >= dt - tcur) { h = dt - tcur; clipped = true; }
       ++attempts;
-      if (ros_step(t, N, frhs, y, f0.data(), J.data(), h, yn.data(), err.data())) {
+      if (ros_step(t, N, frhs, y, f0.data(), J.data(), h, yn.data(), err.data(), o.lu_pivot == 0)) {
         ++res.rejects;
         if (++nsing > 5) { res.status = ST_SINGULAR; break; }
         h_prop = 0.5 * h;
@@ -696,6 +717,12 @@ int oracle_rhs(const OracleMech* m, double p_pa, const double* y, double* f) {
 
 // mode 0: analytic formulas, 1: dual-number AD (the definition)
 int oracle_jac(const OracleMech* m, double p_pa, const double* y, double* J, int mode) {
+  if (mode == 2) {  // one-sided finite differences (the integrator's jac_mode 1)
+    Params<double> P{m->lnA, m->b, m->theta};
+    std::vector<double> f0(m->K + 1);
+    jac_fd(*m, P, 10.0 * p_pa, y, J, f0.data());
+    return 0;
+  }
   Params<double> P{m->lnA, m->b, m->theta};
   if (mode == 1) {
     jac_ad(*m, P, 10.0 * p_pa, y, J);
@@ -731,6 +758,7 @@ int oracle_thermo(const OracleMech* m, double T, double* cpR, double* hRT, doubl
 }
 
 int oracle_lu_factor(int n, double* A, int* piv) { return lu_factor(A, n, piv); }
+int oracle_lu_factor_nopivot(int n, double* A, int* piv) { return lu_factor(A, n, piv, false); }
 void oracle_lu_solve(int n, const double* A, const int* piv, double* b, int trans) { lu_solve(A, n, piv, b, trans); }
 
 // Batched adaptive integration: state is SoA [N][ld] (row 0 T, rows 1..K Y), in place.

@@ -40,7 +40,8 @@ class _Mech(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("max_steps", C.c_int32), ("fac_safe", C.c_double),
-                ("fac_min", C.c_double), ("fac_max", C.c_double), ("h_min", C.c_double)]
+                ("fac_min", C.c_double), ("fac_max", C.c_double), ("h_min", C.c_double),
+                ("jac_mode", C.c_int32), ("lu_pivot", C.c_int32)]
 
 
 _lib = None
@@ -88,8 +89,10 @@ def _as_mech(m):
     return m if isinstance(m, Mech) else Mech(m)
 
 
-def opts(method="ros4", max_steps=100000, fac_safe=0.9, fac_min=0.2, fac_max=6.0, h_min=1e-20):
-    return _Opts(METHOD.get(method, method), max_steps, fac_safe, fac_min, fac_max, h_min)
+def opts(method="ros4", max_steps=100000, fac_safe=0.9, fac_min=0.2, fac_max=6.0, h_min=1e-20, jac_mode=0,
+         lu_pivot=0):
+    """jac_mode 0 analytic / 1 finite differences; lu_pivot 0 partial pivoting / 1 none."""
+    return _Opts(METHOD.get(method, method), max_steps, fac_safe, fac_min, fac_max, h_min, jac_mode, lu_pivot)
 
 
 def gas_constant():
@@ -108,7 +111,7 @@ def jac(mech, p, y, mode="analytic"):
     m = _as_mech(mech)
     y = np.ascontiguousarray(y, np.float64)
     J = np.zeros((m.N, m.N))
-    lib().oracle_jac(C.byref(m.s), C.c_double(p), _p(y), _p(J), 1 if mode == "ad" else 0)
+    lib().oracle_jac(C.byref(m.s), C.c_double(p), _p(y), _p(J), {"analytic": 0, "ad": 1, "fd": 2}[mode])
     return J
 
 
@@ -127,11 +130,12 @@ def thermo(mech, T):
     return cpR, hRT, sR
 
 
-def lu_factor(A):
+def lu_factor(A, pivot=True):
     A = np.array(A, dtype=np.float64, order="C")
     n = A.shape[0]
     piv = np.zeros(n, np.int32)
-    info = lib().oracle_lu_factor(n, _p(A), _p(piv))
+    f = lib().oracle_lu_factor if pivot else lib().oracle_lu_factor_nopivot
+    info = f(n, _p(A), _p(piv))
     return A, piv, info
 
 
