@@ -130,6 +130,9 @@ def main():
     ap.add_argument("--cells", type=int, default=0, help="integrate only the first CELLS cells (profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="per-phase cost of the analytic vs finite-difference Jacobian and pivoted vs unpivoted "
+                         "LU over an atol sweep (the shape of the paper's Figs. 2 and 3)")
     ap.add_argument("--adjoint", action="store_true",
                     help="time chem_integrate_adjoint (gradients of sum_cells[T + w.Y] w.r.t. lnA, b, theta)")
     args = ap.parse_args()
@@ -150,6 +153,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.ablation:
+        return bench_ablation(args)
     if args.adjoint:
         return bench_adjoint(args)
     w = WORKLOADS[args.config]
@@ -250,6 +255,56 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, mech, st0_np)
     print(json.dumps(out), flush=True)
+
+
+def bench_ablation(args):
+    """The 53-species / 325-reaction mechanism (the size of GRI-3.0 in Figs. 2-3)
+    at 13.5 atm and T = 1200 K over dt = 1e-6 s, rtol 1e-6, atol swept: cells/s
+    and the share of each phase for the four combinations of analytic or
+    finite-difference Jacobian and pivoted or unpivoted LU."""
+    import torch
+    from paper_2105_12070_amd import chem
+    from paper_2105_12070_amd.inputs import make_states
+
+    w = WORKLOADS["c4_adj"]
+    mech = w.mechanism()
+    nc = args.cells or 2048
+    st0_np = make_states(mech, nc, 2104, [(1200.0, 1200.0)])
+    p = 13.5 * 101325.0
+    dev = torch.device("cuda:0")
+    m = chem.Mechanism(mech)
+    st0 = torch.tensor(st0_np, device=dev)
+    names = ["jac", "formM", "lu", "stage_f", "solves", "total"]
+    rows = []
+    for atol in (1e-8, 1e-10, 1e-12, 1e-14):
+        for jm, lp, label in ((0, 0, "analytic J + pivoted LU"), (1, 0, "FD J + pivoted LU"),
+                              (0, 1, "analytic J + unpivoted LU"), (1, 1, "FD J + unpivoted LU")):
+            s = st0.clone()
+            h = torch.zeros(nc, dtype=torch.float64, device=dev)
+            steps = torch.zeros(nc, dtype=torch.int32, device=dev)
+            rej = torch.zeros(nc, dtype=torch.int32, device=dev)
+            status = torch.zeros(nc, dtype=torch.int32, device=dev)
+            pc = torch.zeros((nc, 8), dtype=torch.int64, device=dev)
+            opt = chem.Options(phase_cycles=pc, jac_mode=jm, lu_pivot=lp)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chem.integrate(m, s, h, p, w.dt, 1e-6, atol, options=opt, steps=steps, rejects=rej, status=status)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            c = pc.cpu().numpy().astype(np.float64).sum(axis=0)
+            rows.append({"atol": atol, "mode": label, "cells_per_s": nc / el,
+                         "steps_mean": float(steps.float().mean()), "rejects_mean": float(rej.float().mean()),
+                         "failed_cells": int((status != 0).sum()),
+                         "phase_share": {n: float(c[i] / c[5]) for i, n in enumerate(names[:5])}})
+            print(f"# atol {atol:g} {label}: {nc / el:.0f} cells/s, steps {rows[-1]['steps_mean']:.0f}, "
+                  f"jac share {rows[-1]['phase_share']['jac']:.2f}", file=sys.stderr, flush=True)
+    base = [r for r in rows if r["atol"] == 1e-10 and r["mode"].startswith("analytic J + pivoted")][0]
+    print(json.dumps({"metric": "ablation: cells/s and phase shares, analytic vs finite-difference Jacobian, "
+                                "pivoted vs unpivoted LU", "value": base["cells_per_s"], "unit": "cells/s",
+                      "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                      "config": {"workload": f"53 species / 325 reactions, {nc} cells at T = 1200 K, p = 13.5 atm, "
+                                             "dt = 1e-6 s, rtol 1e-6, atol swept"},
+                      "rows": rows}), flush=True)
 
 
 def bench_adjoint(args):

@@ -85,6 +85,10 @@ typedef struct chem_options {
   uint64_t* phase_cycles; /* NULL [NULL], or device [ncells][8] shader-clock cycles per cell:
                              Jacobian pass, forming M, LU, stage f, solves, total, and the
                              reaction and species parts of the Jacobian pass */
+  /* Ablation switches of section 2.3 (N <= 64; they select the instrumented kernel): */
+  int32_t jac_mode;   /* 0 analytic Jacobian [0], 1 one-sided finite differences, column j
+                         from f(y + d_j e_j), d_j = sqrt(eps) max(|y_j|, 1e-10) */
+  int32_t lu_pivot;   /* 0 partial pivoting [0], 1 no pivoting (rows in natural order) */
 } chem_options;
 
 /* Validates (element balance is not required; indices, cp > 0 on

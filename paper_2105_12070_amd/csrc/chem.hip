@@ -433,7 +433,8 @@ int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStrea
   const size_t lds = m->d.lds_bytes + (size_t)wpb * cell_bytes(m->d);
   return with_np(m->d.N, [&](auto npc) -> int {
     constexpr int NP = decltype(npc)::value;
-    auto kern = a.prof ? k_integrate<NP, true> : k_integrate<NP, false>;
+    // the instrumented kernel also carries the ablation switches
+    auto kern = (a.prof || a.jac_fd || a.lu_nopiv) ? k_integrate<NP, true> : k_integrate<NP, false>;
     const void* fn = (const void*)kern;
     if (set_lds_limit<NP>(fn, lds)) return CHEM_EHIP;
     int grid;
@@ -801,6 +802,11 @@ static int fill_common(const chem_mech* m, const chem_options* opt, IntArgs& a) 
   a.ctl.fac_min = o.fac_min;
   a.ctl.fac_max = o.fac_max;
   a.ctl.h_min = o.h_min;
+  if ((o.jac_mode != 0 && o.jac_mode != 1) || (o.lu_pivot != 0 && o.lu_pivot != 1))
+    return fail(CHEM_EINVAL, "jac_mode and lu_pivot must be 0 or 1");
+  if ((o.jac_mode || o.lu_pivot) && m->wg) return fail(CHEM_EUNSUPPORTED, "ablation switches need N <= 64");
+  a.jac_fd = o.jac_mode;
+  a.lu_nopiv = o.lu_pivot;
   return 0;
 }
 
@@ -873,7 +879,7 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
     key.v = {(uintptr_t)state, (uintptr_t)h, (uintptr_t)ncells, (uintptr_t)ld, (uintptr_t)steps,
              (uintptr_t)rejects, (uintptr_t)status, (uintptr_t)s, (uintptr_t)v.wpb, (uintptr_t)v.grid_mult,
              (uintptr_t)ordered, (uintptr_t)m->order, (uintptr_t)m->wg_scr};
-    double dv[5] = {p, dt, rtol, atol, (double)(opt ? opt->method : 0)};
+    double dv[7] = {p, dt, rtol, atol, (double)(opt ? opt->method : 0), (double)a.jac_fd, (double)a.lu_nopiv};
     for (double x : dv) {
       uint64_t u;
       std::memcpy(&u, &x, 8);

@@ -287,9 +287,28 @@ __device__ inline double rhs(const MechView& m, const CellWs& w, double y, doubl
 //   J_kT = (W_k/rho) (dw_k/dT - s_k/T + w_k/T)
 //   J_Tj = -(sum_k hm_k J_kj + f_T cpm_j)/c_p,  J_TT = -(sum_k hm_k J_kT + sum_k cpm_k f_k + f_T dc_p/dT)/c_p
 // (hm, cpm: mass-specific enthalpy and heat capacity).  `row` is scratch.
+// One-sided finite-difference Jacobian (the ablation of section 2.3): column
+// j is (f(y + d_j e_j) - f(y)) / d_j with d_j = sqrt(eps) max(|y_j|, 1e-10)
+// rounded to a representable step; N + 1 evaluations of f.  Returns f(y).
+__device__ inline double jac_fd(const MechView& m, const CellWs& w, double y, double p, int lane) {
+  const int N = m.d.N, S = m.d.S;
+  const double f0 = rhs(m, w, y, p, lane);
+#pragma clang loop unroll(disable)
+  for (int j = 0; j < N; ++j) {
+    const double yj = readlane(y, j);
+    double d = 1.4901161193847656e-08 * fmax(fabs(yj), 1e-10);
+    d = (yj + d) - yj;
+    const double fj = rhs(m, w, lane == j ? yj + d : y, p, lane);
+    if (lane < N) w.J[lane * S + j] = (fj - f0) / d;
+  }
+  wsync();
+  return f0;
+}
+
 template <int NP, bool PROF = false>
 __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, double p, int lane,
-                                  double (&row)[NP], Prof<PROF>* pf = nullptr) {
+                                  double (&row)[NP], Prof<PROF>* pf = nullptr, bool fd = false) {
+  if (PROF && fd) return jac_fd(m, w, y, p, lane);
   const int K = m.d.K, R = m.d.R, N = m.d.N, S = m.d.S;
   const unsigned long long t0 = PROF ? pf->now() : 0ull;
   Mix x;
@@ -446,7 +465,8 @@ __device__ __forceinline__ double recip(double x) {
 // the pivot column is always c0; every register index is static.
 // Returns the 1-based step of a zero pivot, or 0.
 template <int NP, bool BCAST_LDS = CHEM_LU_BCAST_LDS>
-__device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep, double& myrdiag, double* bc) {
+__device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep, double& myrdiag, double* bc,
+                                bool nopiv = false) {
   mystep = lane < N ? -1 : (1 << 20);
   myrdiag = 0.0;
   int info = 0;
@@ -464,9 +484,10 @@ __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep,
       const unsigned kmax = wave_max_u32(key);
       // a zero pivot column is recorded and the factorisation runs on with
       // zero multipliers (no early exit keeps the control flow simple)
-      const bool sing = kmax == 0u;
+      // without pivoting (ablation) the pivot is row k itself
+      const bool sing = nopiv ? !(readlane(c0, k) != 0.0) : kmax == 0u;
       if (sing && info == 0) info = k + 1;
-      const int p = sing ? 0 : uniform_int(__builtin_ctzll(ballot(elig && key == kmax)));
+      const int p = sing ? 0 : (nopiv ? k : uniform_int(__builtin_ctzll(ballot(elig && key == kmax))));
       const double piv = readlane(c0, p);
       const double rp = recip(piv);
       const bool upd = elig && lane != p && !sing;
@@ -613,13 +634,13 @@ template <int NP, bool PROF>
 __device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosTable& tab, double p, int lane,
                                   double y, double f0, double h, double (&row)[NP], double& ynew, double& err,
                                   int& mystep, double& myrdiag, Prof<PROF>& pf, double* kst = nullptr,
-                                  int* srcout = nullptr) {
+                                  int* srcout = nullptr, bool nopiv = false) {
   const int N = m.d.N;
   pf.start();
   const bool okm = form_matrix<NP>(w, N, m.d.S, lane, 1.0 / (tab.gamma * h), row);
   pf.stop(1);
   if (!okm) return 2;
-  const int info = lu_factor<NP>(row, N, lane, mystep, myrdiag, w.bc);
+  const int info = lu_factor<NP>(row, N, lane, mystep, myrdiag, w.bc, PROF && nopiv);
   if (info) {
     pf.stop(2);
     return 1;
@@ -701,7 +722,7 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
   int ntape = 0;
   while (status == ST_OK && t < dt) {
     pf.start();
-    const double f0 = jac_pass<NP, PROF>(m, w, y, a.p, lane, row, &pf);
+    const double f0 = jac_pass<NP, PROF>(m, w, y, a.p, lane, row, &pf, PROF && a.jac_fd);
     pf.stop(0);
     bool fresh = true;
     int nsing = 0;
@@ -716,7 +737,8 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
       if (fresh && ballot(lane < N && !__builtin_isfinite(f0))) { status = ST_NONFINITE; break; }
       double ynew, err;
       const int rc =
-          ros_attempt<NP, PROF>(m, w, kTables[a.method], a.p, lane, y, f0, h, row, ynew, err, mystep, myrdiag, pf);
+          ros_attempt<NP, PROF>(m, w, kTables[a.method], a.p, lane, y, f0, h, row, ynew, err, mystep, myrdiag, pf,
+                                nullptr, nullptr, PROF && a.lu_nopiv);
       if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
       fresh = false;
       if (rc) {
@@ -773,7 +795,7 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
     if (a.rejects) a.rejects[c] = rejects;
     if (a.status) a.status[c] = status;
   }
-  if (PROF && lane < 8) {
+  if (PROF && a.prof && lane < 8) {
     unsigned long long v = 0;
 #pragma unroll
     for (int i = 0; i < 8; ++i)
