@@ -589,9 +589,192 @@ void jac_fd(const OracleMech& m, const Params<double>& P, double p, const double
   }
 }
 
+// ------------------------------------------ extrapolated linearly implicit Euler
+// The Seulex family (the paper's integrator, section 2.3; Hairer & Wanner,
+// Solving ODEs II, section IV.9): over a step H with J = J(y0) frozen, column
+// j (1-based) takes n_j = j linearly implicit Euler substeps of size h = H/n_j,
+//   (I/h - J)(y_{m+1} - y_m) = f(y_m),
+// and the Aitken-Neville table
+//   T_{j,l+1} = T_{j,l} + (T_{j,l} - T_{j-1,l}) / (n_j / n_{j-l} - 1)
+// raises the order by one per column (T_{j,j} has order j).  Column j's error
+// estimate is ||T_{j,j} - T_{j,j-1}||, which scales as H^j.
+constexpr int SX_KMAX = 6;
+
+// Fills T[j][l] (0-based, l <= j < kcols); returns 1 if an iteration matrix is singular.
+// With stab, a stability check in the manner of Hairer & Wanner IV.9 (the
+// second increment of a column must not exceed the first in the scaled norm
+// sc_i = atol + rtol |y0_i|, else return 2); the integrator leaves it off: on
+// these mechanisms it rejects sound steps during fast transients.
+template <class Rhs>
+int seulex_table(int N, Rhs&& frhs, const double* y0, const double* f0, const double* J, double H, int kcols,
+                 std::vector<std::vector<std::vector<double>>>& T, bool pivot, double rtol = 0.0,
+                 double atol = 0.0, bool stab = false) {
+  std::vector<double> M((size_t)N * N), yc(N), f(N), d(N);
+  std::vector<int> piv(N);
+  auto dnorm = [&](const std::vector<double>& v) {
+    double s2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+      const double e = v[i] / (atol + rtol * std::fabs(y0[i]));
+      s2 += e * e;
+    }
+    return std::sqrt(s2 / N);
+  };
+  for (int j = 0; j < kcols; ++j) {
+    const int nj = j + 1;
+    const double h = H / nj;
+    for (int a = 0; a < N; ++a)
+      for (int b = 0; b < N; ++b) M[(size_t)a * N + b] = (a == b ? 1.0 / h : 0.0) - J[(size_t)a * N + b];
+    if (lu_factor(M.data(), N, piv.data(), pivot)) return 1;
+    for (int i = 0; i < N; ++i) yc[i] = y0[i];
+    double del1 = 0.0;
+    for (int mm = 0; mm < nj; ++mm) {
+      if (mm == 0) {
+        for (int i = 0; i < N; ++i) d[i] = f0[i];
+      } else {
+        frhs(yc.data(), f.data());
+        for (int i = 0; i < N; ++i) d[i] = f[i];
+      }
+      lu_solve(M.data(), N, piv.data(), d.data(), 0);
+      for (int i = 0; i < N; ++i) yc[i] += d[i];
+      if (stab) {
+        if (mm == 0) del1 = dnorm(d);
+        else if (mm == 1 && !(dnorm(d) <= del1)) return 2;
+      }
+    }
+    T[j][0] = yc;
+    for (int l = 1; l <= j; ++l) {
+      const double r = (double)(j + 1 - l) / l;  // 1 / (n_j / n_{j-l} - 1) for n_j = j
+      for (int i = 0; i < N; ++i) T[j][l][i] = T[j][l - 1][i] + (T[j][l - 1][i] - T[j - 1][l - 1][i]) * r;
+    }
+  }
+  return 0;
+}
+
+double sx_err(int N, const std::vector<double>& a, const std::vector<double>& b, const double* y0, double rtol,
+              double atol) {
+  double s2 = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double sc = atol + rtol * std::max(std::fabs(y0[i]), std::fabs(a[i]));
+    const double e = (a[i] - b[i]) / sc;
+    s2 += e * e;
+  }
+  return std::sqrt(s2 / N);
+}
+
+// Adaptive Seulex integration of one cell over [0, dt].  Order control: the
+// target column k starts at 3; after an accepted step the next k among k-1,
+// k, k+1 minimises the work per unit step A_j / H_j, with A_j = sum_{i<=j}
+// (n_i + 1) (substeps plus one factorisation per column) and H_j the step
+// that column j's error proposes, H fac_safe err_j^(-1/j) clamped by
+// fac_min / fac_max.  Rejections keep k and take H_k; the controller's other
+// rules (clipping to dt, no growth after a rejection, h_out, limits, halving
+// on a singular matrix) are those of the Rosenbrock path.
+CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, double rtol, double atol,
+                                 const OracleOpts& o, double* y, double* h_io, std::vector<double>* hs_out) {
+  const int N = m.K + 1;
+  Params<double> P{m.lnA, m.b, m.theta};
+  auto frhs = [&](const double* yy, double* ff) { rhs(m, P, p, yy, ff); };
+  CellResult res{ST_OK, 0, 0};
+  std::vector<double> f0(N), J((size_t)N * N);
+  std::vector<std::vector<std::vector<double>>> T(SX_KMAX, std::vector<std::vector<double>>(SX_KMAX,
+                                                  std::vector<double>(N)));
+  double A[SX_KMAX + 2];
+  A[0] = 0.0;
+  for (int j = 1; j <= SX_KMAX + 1; ++j) A[j] = A[j - 1] + (j + 1);
+  double h_prop = (std::isfinite(*h_io) && *h_io > 0.0) ? std::min(*h_io, dt) : dt;
+  if (!all_finite(y, N) || !(y[0] > 0.0)) {
+    res.status = ST_NONFINITE;
+    *h_io = h_prop;
+    return res;
+  }
+  int k = 3;
+  double tcur = 0.0;
+  bool rejected_last = false;
+  int attempts = 0;
+  auto hopt = [&](double H, double err, int j) {
+    return H * std::min(o.fac_max, std::max(o.fac_min, o.fac_safe * std::pow(err, -1.0 / j)));
+  };
+  while (tcur < dt) {
+    if (o.jac_mode == 1) jac_fd(m, P, p, y, J.data(), f0.data());
+    else jac_analytic(m, P, p, y, J.data(), f0.data());
+    if (!all_finite(f0.data(), N) || !all_finite(J.data(), N * N)) { res.status = ST_NONFINITE; break; }
+    int nsing = 0;
+    bool accepted = false;
+    while (!accepted) {
+      if (attempts >= o.max_steps) { res.status = ST_TOO_MANY_STEPS; break; }
+      if (!(h_prop >= o.h_min)) { res.status = ST_UNDERFLOW; break; }
+      double H = h_prop;
+      bool clipped = false;
+      if (H >= dt - tcur) { H = dt - tcur; clipped = true; }
+      ++attempts;
+      const int rc = seulex_table(N, frhs, y, f0.data(), J.data(), H, k, T, o.lu_pivot == 0, rtol, atol);
+      if (rc == 1) {
+        ++res.rejects;
+        if (++nsing > 5) { res.status = ST_SINGULAR; break; }
+        h_prop = 0.5 * H;
+        rejected_last = true;
+        continue;
+      }
+      if (rc == 2) {  // unstable substeps
+        ++res.rejects;
+        h_prop = 0.5 * H;
+        rejected_last = true;
+        continue;
+      }
+      const std::vector<double>& yk = T[k - 1][k - 1];
+      const double errk = sx_err(N, yk, T[k - 1][k - 2], y, rtol, atol);
+      if (!std::isfinite(errk) || !all_finite(yk.data(), N)) {
+        ++res.rejects;
+        h_prop = o.fac_min * H;
+        rejected_last = true;
+        continue;
+      }
+      const double Hk = hopt(H, errk, k);
+      // column k-1's proposal (for the order decision), from the same step start
+      double Hk1 = 0.0;
+      if (k >= 3) {
+        const double e1 = sx_err(N, T[k - 2][k - 2], T[k - 2][k - 3], y, rtol, atol);
+        if (std::isfinite(e1)) Hk1 = hopt(H, e1, k - 1);
+      }
+      if (errk <= 1.0) {
+        accepted = true;
+        ++res.steps;
+        if (hs_out) hs_out->push_back(H);
+        tcur = clipped ? dt : tcur + H;
+        for (int i = 0; i < N; ++i) y[i] = yk[i];
+        int knew = k;
+        double hnew = Hk;
+        if (k >= 3 && Hk1 > 0.0 && A[k - 1] / Hk1 < 0.8 * (A[k] / Hk)) {
+          knew = k - 1;
+          hnew = Hk1;
+        } else if (k < SX_KMAX && (k == 2 || Hk1 <= 0.0 || A[k] / Hk < 0.9 * (A[k - 1] / Hk1))) {
+          knew = k + 1;
+          hnew = Hk * (A[k + 1] / A[k]);
+        }
+        if (rejected_last) {
+          hnew = std::min(hnew, H);
+          knew = std::min(knew, k);
+        }
+        if (clipped) hnew = std::max(hnew, h_prop);
+        h_prop = hnew;
+        k = knew;
+        rejected_last = false;
+      } else {
+        ++res.rejects;
+        h_prop = Hk;
+        rejected_last = true;
+      }
+    }
+    if (res.status != ST_OK) break;
+  }
+  *h_io = std::min(h_prop, dt);
+  return res;
+}
+
 // Adaptive integration of one cell over [0, dt] (controller constants in opts).
 CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol, double atol, const OracleOpts& o,
                           double* y, double* h_io, std::vector<double>* hs_out) {
+  if (o.method == 3) return integrate_cell_seulex(m, p, dt, rtol, atol, o, y, h_io, hs_out);
   const int N = m.K + 1;
   const Table t = table_of(o.method);
   Params<double> P{m.lnA, m.b, m.theta};
@@ -842,6 +1025,26 @@ int oracle_ros_test(int method, int problem, double h, int nsteps, const double*
     yout[i] = y[i];
     errout[i] = err[i];
   }
+  return 0;
+}
+
+// Fixed-column extrapolated linearly implicit Euler on the built-in test
+// problems (order checks): nsteps steps of size H, result T_{k,k} each step.
+int oracle_sx_test(int problem, double H, int nsteps, int kcols, const double* y0, double* yout) {
+  const int N = problem == 0 ? 2 : 1;
+  const double lam = problem == 0 ? 0.0 : y0[1];
+  std::vector<double> y(y0, y0 + N), f0(N), J((size_t)N * N);
+  std::vector<std::vector<std::vector<double>>> T(SX_KMAX, std::vector<std::vector<double>>(SX_KMAX,
+                                                  std::vector<double>(N)));
+  auto frhs = [&](const double* yy, double* ff) { test_rhs(problem, yy, ff, lam); };
+  if (kcols < 1 || kcols > SX_KMAX) return 2;
+  for (int s = 0; s < nsteps; ++s) {
+    test_rhs(problem, y.data(), f0.data(), lam);
+    test_jac(problem, y.data(), J.data(), lam);
+    if (seulex_table(N, frhs, y.data(), f0.data(), J.data(), H, kcols, T, true)) return 1;
+    y = T[kcols - 1][kcols - 1];
+  }
+  for (int i = 0; i < N; ++i) yout[i] = y[i];
   return 0;
 }
 

@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "chem_oracle.cpp")
 _LIB = os.path.join(_HERE, "libchem_oracle.so")
 
 STATUS = {0: "OK", 1: "TOO_MANY_STEPS", 2: "STEP_UNDERFLOW", 3: "SINGULAR", 4: "NONFINITE"}
-METHOD = {"ros4": 0, "rodas3": 1, "euler": 2}
+METHOD = {"ros4": 0, "rodas3": 1, "euler": 2, "seulex": 3}
 
 
 def build(force: bool = True) -> str:
@@ -209,6 +209,17 @@ def ros_test(method, problem, h, nsteps, y0):
     if rc:
         raise RuntimeError("singular")
     return yo, eo
+
+
+def sx_test(problem, H, nsteps, kcols, y0):
+    """Fixed-column extrapolated linearly implicit Euler on a built-in test problem."""
+    y0 = np.ascontiguousarray(y0, np.float64)
+    n = 2 if problem == 0 else 1
+    yo = np.zeros(n)
+    rc = lib().oracle_sx_test(problem, C.c_double(H), nsteps, kcols, _p(y0), _p(yo))
+    if rc:
+        raise RuntimeError("sx_test failed")
+    return yo
 
 
 def num_threads():
