@@ -12,6 +12,7 @@
 #include "../../include/chem.h"
 #include "chem_adjoint.hpp"
 #include "chem_wg.hpp"
+#include "chem_seulex.hpp"
 #include "chem_cell.hpp"
 
 using namespace chem;
@@ -53,6 +54,32 @@ __global__ __launch_bounds__(max_threads<NP>()) void k_integrate(IntArgs a) {
   while (idx < a.ncells) {
     const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
     integrate_cell<NP, PROF>(m, w, a, c);
+    if (!a.queue) break;
+    int v = 0;
+    if (lane_id() == 0) v = atomicAdd(a.queue, 1);
+    idx = uniform_int(__shfl(v, 0));
+  }
+}
+
+// The same launch structure with the Seulex-family integrator.
+template <int NP, bool PROF>
+__global__ __launch_bounds__(max_threads<NP>()) void k_integrate_sx(IntArgs a) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  stage_blob(lds, a.blob, a.d.lds_bytes);
+  const MechView m = make_view(lds, a);
+  const int wv = threadIdx.x / WAVE;
+  const CellWs w = make_ws((double*)(lds + a.d.lds_bytes) + (size_t)wv * a.cell_doubles, a.d);
+  int64_t idx;
+  if (a.queue) {
+    int v = 0;
+    if (lane_id() == 0) v = atomicAdd(a.queue, 1);
+    idx = uniform_int(__shfl(v, 0));
+  } else {
+    idx = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
+  }
+  while (idx < a.ncells) {
+    const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
+    integrate_cell_sx<NP, PROF>(m, w, a, c);
     if (!a.queue) break;
     int v = 0;
     if (lane_id() == 0) v = atomicAdd(a.queue, 1);
@@ -434,7 +461,8 @@ int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStrea
   return with_np(m->d.N, [&](auto npc) -> int {
     constexpr int NP = decltype(npc)::value;
     // the instrumented kernel also carries the ablation switches
-    auto kern = (a.prof || a.jac_fd || a.lu_nopiv) ? k_integrate<NP, true> : k_integrate<NP, false>;
+    auto kern = a.method == 2 ? (a.prof ? k_integrate_sx<NP, true> : k_integrate_sx<NP, false>)
+                : (a.prof || a.jac_fd || a.lu_nopiv) ? k_integrate<NP, true> : k_integrate<NP, false>;
     const void* fn = (const void*)kern;
     if (set_lds_limit<NP>(fn, lds)) return CHEM_EHIP;
     int grid;
@@ -792,7 +820,9 @@ static int fill_common(const chem_mech* m, const chem_options* opt, IntArgs& a) 
   o.fac_max = 6.0;
   o.h_min = 1e-20;
   if (opt) o = *opt;
-  if (o.method != 0 && o.method != 1) return fail(CHEM_EINVAL, "method must be 0 (ROS4) or 1 (Rodas3)");
+  if (o.method < 0 || o.method > 2) return fail(CHEM_EINVAL, "method must be 0 (ROS4), 1 (Rodas3) or 2 (Seulex)");
+  if (o.method == 2 && (m->wg || o.jac_mode || o.lu_pivot))
+    return fail(CHEM_EUNSUPPORTED, "the Seulex integrator runs on N <= 64 with the analytic Jacobian and pivoted LU");
   if (o.max_steps < 1 || !(o.fac_min > 0.0) || !(o.fac_max >= 1.0) || !(o.fac_safe > 0.0) || !(o.h_min >= 0.0))
     return fail(CHEM_EINVAL, "invalid controller options");
   a.method = o.method;

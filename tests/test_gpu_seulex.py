@@ -1,0 +1,85 @@
+"""Parity of the Seulex-family integrator (method 2) with the oracle's."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from paper_2105_12070_amd.inputs import WORKLOADS  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def chem():
+    from paper_2105_12070_amd import chem as c
+    assert torch.cuda.is_available()
+    return c
+
+
+def run(chem, mech, st0, p, dt, rtol, atol, **opt):
+    m = chem.Mechanism(mech)
+    nc = st0.shape[1]
+    s = torch.tensor(st0, device=DEV)
+    h = torch.zeros(nc, dtype=torch.float64, device=DEV)
+    steps = torch.zeros(nc, dtype=torch.int32, device=DEV)
+    rej = torch.zeros(nc, dtype=torch.int32, device=DEV)
+    status = torch.zeros(nc, dtype=torch.int32, device=DEV)
+    chem.integrate(m, s, h, p, dt, rtol, atol, options=chem.Options(method=2, **opt), steps=steps, rejects=rej,
+                   status=status)
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), h.cpu().numpy(), steps.cpu().numpy(), rej.cpu().numpy(), status.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,nc,dt", [("c1_10sp", 128, None), ("c2_54sp", 24, 1e-7), ("c4_adj", 16, 1e-7)])
+def test_seulex_tight_parity(chem, name, nc, dt):
+    w = WORKLOADS[name]
+    mech = w.mechanism()
+    st0 = w.states(mech, nc)
+    dt = dt or w.dt
+    rtol, atol = 1e-10, 1e-14
+    got, h, steps, rej, status = run(chem, mech, st0, w.p_pa, dt, rtol, atol)
+    assert np.all(status == 0)
+    ref, href, rs, rr, rst = oracle.integrate(mech, st0, None, w.p_pa, dt, rtol, atol, method="seulex")
+    assert np.all(rst == 0)
+    dev_ = np.abs(got - ref)
+    rel = dev_ / (np.abs(ref) + 100 * atol)
+    same = (steps == rs) & (rej == rr)
+    print(f"[seulex {name}] max rel dev {rel.max():.3e}; identical (steps, rejects) {same.mean():.2f}; "
+          f"steps gpu {steps[:6]} oracle {rs[:6]}")
+    assert np.all(dev_ <= 1e-8 * np.abs(ref) + 100 * atol)
+
+
+def test_seulex_metric_and_launch_shapes(chem):
+    w = WORKLOADS["c2_54sp"]
+    mech = w.mechanism()
+    st0 = w.states(mech, 203)
+    a = run(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, persistent=0, waves_per_block=1)
+    b = run(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, persistent=1)
+    assert np.all(a[4] == 0)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    idx = np.arange(0, 203, 17)
+    ref, href, rs, rr, rst = oracle.integrate(mech, st0[:, idx], None, w.p_pa, w.dt, w.rtol, w.atol,
+                                              method="seulex")
+    bound = 100 * (w.rtol * np.abs(ref) + w.atol)
+    print(f"[seulex c2 metric] max dev / bound {np.max(np.abs(a[0][:, idx] - ref) / bound):.3e}; "
+          f"mean steps {a[2].mean():.1f}")
+    assert np.all(np.abs(a[0][:, idx] - ref) <= bound)
+
+
+def test_seulex_unsupported_combinations(chem):
+    w = WORKLOADS["c1_10sp"]
+    mech = w.mechanism()
+    m = chem.Mechanism(mech)
+    s = torch.tensor(w.states(mech, 4), device=DEV)
+    h = torch.zeros(4, dtype=torch.float64, device=DEV)
+    with pytest.raises(chem.ChemError):
+        chem.integrate(m, s, h, w.p_pa, w.dt, w.rtol, w.atol, options=chem.Options(method=2, jac_mode=1))
+    with pytest.raises(chem.ChemError):
+        chem.integrate_adjoint(m, s, h, w.p_pa, w.dt, w.rtol, w.atol, torch.ones_like(s),
+                               options=chem.Options(method=2))
+    with pytest.raises(chem.ChemError):
+        chem.integrate(m, s, h, w.p_pa, w.dt, w.rtol, w.atol, options=chem.Options(method=3))
