@@ -19,7 +19,12 @@
 //    control over one CFD time step (section 2.3: rtol/atol, a sub-step that
 //    persists between calls);
 //  * the tangent-linear model of the integration with its accepted step
-//    sequence frozen (forward-mode duals through every step).
+//    sequence frozen (forward-mode duals through every step);
+//  * the Seulex-family integrator of section 2.3 (extrapolated linearly
+//    implicit Euler with order control);
+//  * the ablation options of section 2.3 (one-sided finite-difference
+//    Jacobian, LU without pivoting);
+//  * reference-cell mapping of low-reactivity cells (section 2.2).
 //
 // Units: CGS inside (p in dyn/cm^2, R in erg/mol/K, C in mol/cm^3); the C API
 // takes p in Pa.
@@ -963,6 +968,79 @@ int oracle_integrate(const OracleMech* m, int64_t ncells, int64_t ld, double* st
     if (status) status[c] = r.status;
   }
   (void)nthreads;
+  return 0;
+}
+
+// Reference-cell mapping.  Section 2.2 describes DLBFoam's zonal reference
+// mapping: in low-reactivity (ambient) regions the chemistry solution of one
+// reference cell is mapped onto the others instead of integrating each.  The
+// paper gives no criterion; the one here is this library's reading:
+//  * indicator z_c = z0 + sum_k w_k Y_k (species in index order, each term a
+//    fused multiply-add); cell c is in the low-reactivity zone if z_c <= z_max
+//    (a linear indicator covers a fuel mass fraction and Bilger's mixture
+//    fraction alike);
+//  * the reference r is the zone cell of lowest index;
+//  * a zone cell c != r is mapped if |T_c - T_r| <= dT: it is not integrated
+//    and takes the reference's increment per unit mass,
+//    Phi_c(dt) = Phi_c(0) + (Phi_r(dt) - Phi_r(0)), with h_c = h_r after the
+//    call, zero steps and rejects, and the reference's status;
+//  * every other cell, r included, is integrated.
+// ref_of[c] receives r for a mapped cell, -1 otherwise.
+int oracle_integrate_refmap(const OracleMech* m, int64_t ncells, int64_t ld, double* state, double* h, double p_pa,
+                            double dt, double rtol, double atol, const OracleOpts* o, const double* w, double z0,
+                            double z_max, double dT, int32_t* ref_of, int32_t* steps, int32_t* rejects,
+                            int32_t* status, int nthreads) {
+  const int N = m->K + 1;
+  std::vector<char> zone(ncells, 0);
+  int64_t r = -1;
+  for (int64_t c = 0; c < ncells; ++c) {
+    double z = z0;
+    for (int k = 0; k < m->K; ++k) z = std::fma(w[k], state[(size_t)(k + 1) * ld + c], z);
+    zone[c] = z <= z_max;
+    if (zone[c] && r < 0) r = c;
+  }
+  std::vector<int64_t> active;
+  for (int64_t c = 0; c < ncells; ++c) {
+    const bool mapped = r >= 0 && c != r && zone[c] && std::fabs(state[c] - state[r]) <= dT;
+    ref_of[c] = mapped ? (int32_t)r : -1;
+    if (!mapped) active.push_back(c);
+  }
+  std::vector<double> y0r(N);
+  if (r >= 0)
+    for (int i = 0; i < N; ++i) y0r[i] = state[(size_t)i * ld + r];
+  // the unmapped cells, gathered into a dense SoA block and integrated
+  const int64_t na = (int64_t)active.size();
+  std::vector<double> sub((size_t)N * na), hsub(na);
+  std::vector<int32_t> ssub(na), rsub(na), stsub(na);
+  for (int64_t j = 0; j < na; ++j) {
+    for (int i = 0; i < N; ++i) sub[(size_t)i * na + j] = state[(size_t)i * ld + active[j]];
+    hsub[j] = h[active[j]];
+  }
+  oracle_integrate(m, na, na, sub.data(), hsub.data(), p_pa, dt, rtol, atol, o, ssub.data(), rsub.data(),
+                   stsub.data(), nthreads);
+  int32_t st_r = 0;
+  double h_r = 0.0;
+  for (int64_t j = 0; j < na; ++j) {
+    const int64_t c = active[j];
+    for (int i = 0; i < N; ++i) state[(size_t)i * ld + c] = sub[(size_t)i * na + j];
+    h[c] = hsub[j];
+    if (steps) steps[c] = ssub[j];
+    if (rejects) rejects[c] = rsub[j];
+    if (status) status[c] = stsub[j];
+    if (c == r) {
+      st_r = stsub[j];
+      h_r = hsub[j];
+    }
+  }
+  for (int64_t c = 0; c < ncells; ++c) {
+    if (ref_of[c] < 0) continue;
+    for (int i = 0; i < N; ++i)
+      state[(size_t)i * ld + c] = state[(size_t)i * ld + c] + (state[(size_t)i * ld + r] - y0r[i]);
+    h[c] = h_r;
+    if (steps) steps[c] = 0;
+    if (rejects) rejects[c] = 0;
+    if (status) status[c] = st_r;
+  }
   return 0;
 }
 

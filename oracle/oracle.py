@@ -159,6 +159,26 @@ def integrate(mech, state, h, p, dt, rtol, atol, method="ros4", max_steps=100000
     return st, hh, steps, rej, status
 
 
+def integrate_refmap(mech, state, h, p, dt, rtol, atol, weight, z0, z_max, dT, method="ros4", max_steps=100000,
+                     nthreads=0, **kw):
+    """Integration with reference-cell mapping (see oracle_integrate_refmap);
+    returns (state, h, steps, rejects, status, ref_of)."""
+    m = _as_mech(mech)
+    st = np.array(state, dtype=np.float64, order="C")
+    N, nc = st.shape
+    hh = np.array(h, dtype=np.float64) if h is not None else np.zeros(nc)
+    w = np.ascontiguousarray(weight, np.float64)
+    assert w.shape == (N - 1,)
+    steps, rej, status = np.zeros(nc, np.int32), np.zeros(nc, np.int32), np.zeros(nc, np.int32)
+    ref_of = np.zeros(nc, np.int32)
+    o = opts(method, max_steps, **kw)
+    lib().oracle_integrate_refmap(C.byref(m.s), C.c_int64(nc), C.c_int64(nc), _p(st), _p(hh), C.c_double(p),
+                                  C.c_double(dt), C.c_double(rtol), C.c_double(atol), C.byref(o), _p(w),
+                                  C.c_double(z0), C.c_double(z_max), C.c_double(dT), _p(ref_of), _p(steps),
+                                  _p(rej), _p(status), C.c_int(nthreads))
+    return st, hh, steps, rej, status, ref_of
+
+
 def integrate_record(mech, y0, h, p, dt, rtol, atol, method="ros4", max_steps=100000, cap=200000, **kw):
     """One cell; returns (y, h_out, hs, status, rejects)."""
     m = _as_mech(mech)

@@ -248,6 +248,9 @@ class Workload:
     floor: float = 0.0
     notes: str = ""
     pool: str | None = None  # file of pre-relaxed states to sample cells from
+    ambient: str | None = None  # file of an ambient-zone state (zonal workload)
+    ambient_frac: float = 0.0   # share of cells that are ambient
+    ambient_jitter: float = 0.0  # ambient T = T_ambient + U(-jitter, jitter) K
 
     @property
     def N(self):
@@ -261,8 +264,29 @@ class Workload:
         mech = mech if mech is not None else self.mechanism()
         if self.pool is not None:
             return pool_states(self.pool, n_cells or self.n_cells, self.state_seed)
-        return make_states(mech, n_cells or self.n_cells, self.state_seed, list(self.T_ranges),
-                           self.fractions, self.alpha, self.majors, self.floor)
+        st = make_states(mech, n_cells or self.n_cells, self.state_seed, list(self.T_ranges),
+                         self.fractions, self.alpha, self.majors, self.floor)
+        if self.ambient is not None:
+            # a seeded share of the cells is replaced by the ambient state with a
+            # jittered temperature, scattered over the index range
+            amb = np.load(os.path.join(POOL_DIR, self.ambient), allow_pickle=False)
+            n = st.shape[1]
+            rng = _rng(self.state_seed + 1)
+            is_amb = rng.random(n) < self.ambient_frac
+            jit = rng.uniform(-self.ambient_jitter, self.ambient_jitter, n)
+            st[:, is_amb] = amb[:, None]
+            st[0, is_amb] += jit[is_amb]
+        return st
+
+    def refmap_params(self) -> dict:
+        """Reference-mapping parameters of a zonal workload: the indicator is the
+        mass fraction of the species scarcest in the ambient state (absent from
+        the zone, present in every reacting cell), the zone threshold is atol,
+        and the temperature window is the ambient jitter."""
+        amb = np.load(os.path.join(POOL_DIR, self.ambient), allow_pickle=False)
+        w = np.zeros(self.n_species)
+        w[int(np.argmin(amb[1:]))] = 1.0
+        return dict(weight=w, z0=0.0, z_max=self.atol, dT=self.ambient_jitter)
 
 
 POOL_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden")
@@ -292,6 +316,12 @@ WORKLOADS = {
     # adjoint workload: 53 species / 325 reactions, 16,384 cells, 1 atm
     "c4_adj": Workload("c4_adj", 53, 325, 32, 16, 16384, ATM, 1e-6, ((1200.0, 2200.0),), None,
                        1004, 2004),
+    # reference-mapping workload: the 54-species mechanism, 65,536 cells, 75% of
+    # them an ambient zone (one near-equilibrium state, T jittered by +-2 K)
+    # scattered among reacting cells drawn as in c2_54sp
+    "zonal_54sp": Workload("zonal_54sp", 54, 270, 27, 14, 65536, 60e5, 1e-6,
+                           ((700.0, 1000.0), (1800.0, 2600.0)), (0.8, 0.2), 1002, 2007,
+                           ambient="zonal_ambient_state.npy", ambient_frac=0.75, ambient_jitter=2.0),
     # large mechanism: 150 species / 1000 reactions, 131,072 cells, 40 bar
     "c5_150sp": Workload("c5_150sp", 150, 1000, 100, 50, 131072, 40e5, 1e-6,
                          ((800.0, 2400.0),), None, 1005, 2005, alpha=0.5, majors=20,

@@ -20,3 +20,19 @@ def test_pool_hash_and_sampling():
     cols = {c.tobytes() for c in pool.T}
     assert all(c.tobytes() in cols for c in st.T)
     assert np.all(np.abs(st[1:].sum(axis=0) - 1.0) < 1e-12)
+
+
+def test_ambient_state_hash_and_zonal_workload():
+    amb = np.load(os.path.join(POOL_DIR, "zonal_ambient_state.npy"), allow_pickle=False)
+    meta = json.load(open(os.path.join(POOL_DIR, "zonal_ambient_state.json")))
+    assert list(amb.shape) == meta["shape"] == [55]
+    assert hashlib.sha256(np.ascontiguousarray(amb).tobytes()).hexdigest() == meta["sha256"]
+    w = WORKLOADS["zonal_54sp"]
+    st = w.states(n_cells=4000)
+    is_amb = np.all(st[1:] == amb[1:, None], axis=0)
+    assert abs(is_amb.mean() - 0.75) < 0.03
+    assert np.all(np.abs(st[0, is_amb] - amb[0]) <= 2.0)
+    rm = w.refmap_params()
+    f = int(np.nonzero(rm["weight"])[0][0])
+    # the indicator species is absent from the ambient zone and present in every reacting cell
+    assert amb[1 + f] <= rm["z_max"] < st[1 + f, ~is_amb].min()
