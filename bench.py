@@ -137,6 +137,8 @@ def main():
                          "LU over an atol sweep (the shape of the paper's Figs. 2 and 3)")
     ap.add_argument("--adjoint", action="store_true",
                     help="time chem_integrate_adjoint (gradients of sum_cells[T + w.Y] w.r.t. lnA, b, theta)")
+    ap.add_argument("--refmap", action="store_true",
+                    help="zonal workload with and without reference-cell mapping of the ambient zone")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the cells are independent, and the multi-GPU "
@@ -159,6 +161,8 @@ def main():
         return bench_ablation(args)
     if args.adjoint:
         return bench_adjoint(args)
+    if args.refmap:
+        return bench_refmap(args)
     w = WORKLOADS[args.config]
     mech = w.mechanism()
     st0_np = w.states(mech)
@@ -211,12 +215,12 @@ def main():
     if np.any(st != 0):
         print(f"# warning: {np.sum(st != 0)} cells with nonzero status {np.bincount(st)}", file=sys.stderr)
     fm = flop_model(mech)
-    f_att = fm["f_att"]
+    work = None
     if args.method == "seulex":
-        # estimate: four extrapolation columns per attempt (4 factorisations, 1+2+3+4 substeps)
-        N = w.N
-        f_att = 4 * (N * N + fm["f_lu"]) + 10 * fm["f_solve"] + 9 * fm["f_rhs"] + 10 * N
-    flops = float(np.sum((sp + rj) * f_att + sp * fm["f_step"]))
+        work = seulex_work(chem, m, st0, w, sp)
+        flops = work.pop("flops")
+    else:
+        flops = float(np.sum((sp + rj) * fm["f_att"] + sp * fm["f_step"]))
     achieved = flops / (kern_ms * 1e-3) / 1e12
 
     plain = None
@@ -260,8 +264,109 @@ def main():
         "steps_percentiles_0_50_90_99_100": np.percentile(sp, [0, 50, 90, 99, 100]).tolist(),
         "plain_one_cell_per_block_cells_per_s": plain,
     }
+    if work:
+        out["seulex_work"] = work
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, mech, st0_np)
+    print(json.dumps(out), flush=True)
+
+
+def seulex_work(chem, m, st0, w, steps_timed):
+    """FLOPs of one Seulex launch from the instrumented kernel's counters
+    (factorisations and substeps per cell), taken in an untimed run with the
+    same arithmetic: per factorisation N^2 + F_LU (form M, LU); per substep
+    F_solve + N; per substep after a column's first F_rhs + 3N (f and the
+    extrapolation table); per attempt 10N (error norms); per step F_jac."""
+    import torch
+    mech = w.mechanism()
+    fm = flop_model(mech)
+    N = w.N
+    nc = st0.shape[1]
+    s = st0.clone()
+    h = torch.zeros(nc, dtype=torch.float64, device=st0.device)
+    steps = torch.zeros(nc, dtype=torch.int32, device=st0.device)
+    rej = torch.zeros(nc, dtype=torch.int32, device=st0.device)
+    pc = torch.zeros((nc, 8), dtype=torch.int64, device=st0.device)
+    chem.integrate(m, s, h, w.p_pa, w.dt, w.rtol, w.atol, options=chem.Options(method=2, phase_cycles=pc),
+                   steps=steps, rejects=rej)
+    torch.cuda.synchronize()
+    sp = steps.cpu().numpy().astype(np.int64)
+    rj = rej.cpu().numpy().astype(np.int64)
+    pcn = pc.cpu().numpy()
+    nlu, nsub = pcn[:, 6].astype(np.float64), pcn[:, 7].astype(np.float64)
+    if not np.array_equal(sp, steps_timed):
+        raise RuntimeError("instrumented Seulex run took other steps than the timed run")
+    flops = float(np.sum(nlu * (N * N + fm["f_lu"]) + nsub * (fm["f_solve"] + N)
+                         + (nsub - nlu) * (fm["f_rhs"] + 3 * N) + (sp + rj) * 10 * N + sp * fm["f_step"]))
+    return {"flops": flops, "lu_per_attempt": float(nlu.sum() / (sp + rj).sum()),
+            "substeps_per_attempt": float(nsub.sum() / (sp + rj).sum())}
+
+
+def bench_refmap(args):
+    """The zonal workload (75% ambient-zone cells among reacting ones): cells/s
+    with reference-cell mapping against the same integration without it, the
+    share of cells mapped, and the mapping error (mapped cells against their
+    own integration)."""
+    import torch
+    from paper_2105_12070_amd import chem
+
+    w = WORKLOADS["zonal_54sp"]
+    mech = w.mechanism()
+    st0_np = w.states(mech)
+    if args.cells:
+        st0_np = np.ascontiguousarray(st0_np[:, :args.cells])
+    nc = st0_np.shape[1]
+    dev = torch.device("cuda:0")
+    m = chem.Mechanism(mech)
+    rm = w.refmap_params()
+    st0 = torch.tensor(st0_np, device=dev)
+    state = st0.clone()
+    h = torch.zeros(nc, dtype=torch.float64, device=dev)
+    steps = torch.zeros(nc, dtype=torch.int32, device=dev)
+    status = torch.zeros(nc, dtype=torch.int32, device=dev)
+    ref_of = torch.zeros(nc, dtype=torch.int32, device=dev)
+    refmap = chem.RefMap(torch.tensor(rm["weight"], device=dev), rm["z0"], rm["z_max"], rm["dT"], ref_of)
+    opts = {"mapped": chem.Options(refmap=refmap), "unmapped": chem.Options()}
+
+    def timed(opt):
+        for _ in range(args.warmup):
+            state.copy_(st0)
+            h.zero_()
+            chem.integrate(m, state, h, w.p_pa, w.dt, w.rtol, w.atol, options=opt, steps=steps, status=status)
+        torch.cuda.synchronize()
+        el = 0.0
+        for _ in range(args.steps):
+            state.copy_(st0)
+            h.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chem.integrate(m, state, h, w.p_pa, w.dt, w.rtol, w.atol, options=opt, steps=steps, status=status)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+        return el, state.cpu().numpy(), steps.cpu().numpy(), status.cpu().numpy()
+
+    el_m, out_m, steps_m, st_m = timed(opts["mapped"])
+    rof = ref_of.cpu().numpy()
+    el_u, out_u, steps_u, st_u = timed(opts["unmapped"])
+    mapped = rof >= 0
+    err = np.abs(out_m - out_u)[:, mapped]
+    scale = w.rtol * np.abs(out_u[:, mapped]) + w.atol
+    value = nc * args.steps / el_m
+    out = {"metric": "cells/s with reference-cell mapping (zonal workload)", "value": value, "unit": "cells/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el_m * 1e3 / args.steps,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"zonal_54sp: 54 species / 270 reactions, {nc} cells (75% ambient zone, "
+                                  f"T jittered by 2 K), p = {w.p_pa:g} Pa, dt = {w.dt:g} s, rtol {w.rtol:g}, "
+                                  f"atol {w.atol:g}, ROS4; zone: Y_{int(np.argmax(rm['weight']))} <= {rm['z_max']:g}, "
+                                  f"dT = {rm['dT']:g} K"},
+           "unmapped_cells_per_s": nc * args.steps / el_u, "speedup": el_u / el_m,
+           "mapped_fraction": float(mapped.mean()),
+           "steps_total": {"mapped_run": int(steps_m.astype(np.int64).sum()),
+                           "unmapped_run": int(steps_u.astype(np.int64).sum())},
+           "mapping_error": {"max_over_tol": float((err / scale).max()) if mapped.any() else 0.0,
+                             "mean_over_tol": float((err / scale).mean()) if mapped.any() else 0.0,
+                             "max_T_K": float(err[0].max()) if mapped.any() else 0.0},
+           "failed_cells": int((st_m != 0).sum() + (st_u != 0).sum())}
     print(json.dumps(out), flush=True)
 
 

@@ -66,6 +66,30 @@ typedef struct chem_mech_desc {
 
 typedef struct chem_mech chem_mech; /* opaque, library-owned */
 
+/* Reference-cell mapping of low-reactivity cells (section 2.2: the chemistry
+ * solution of one reference cell is mapped onto cells of an ambient zone
+ * instead of integrating each; the paper gives no criterion, this one is the
+ * library's):
+ *  - a cell is in the zone if z = z0 + sum_k weight[k] Y_k <= z_max (summed in
+ *    species order with fused multiply-adds; a fuel mass fraction or Bilger's
+ *    mixture fraction are such linear indicators);
+ *  - the reference is the zone cell of lowest index; it is integrated;
+ *  - a zone cell whose T is within dT of the reference's is mapped: not
+ *    integrated, it takes the reference's increment per unit mass,
+ *    Phi(dt) = Phi(0) + (Phi_ref(dt) - Phi_ref(0)), the reference's h and
+ *    status, and zero steps and rejects (also when the reference failed);
+ *  - every other cell is integrated as without mapping.
+ * The decisions are exact (no tolerance): they are taken in FP64 on the input
+ * state in the order stated. */
+typedef struct chem_refmap {
+  const double* weight; /* device [K], caller-owned, read during the call */
+  double z0;            /* indicator offset */
+  double z_max;         /* zone threshold (not NaN) */
+  double dT;            /* temperature window in K (>= 0; +inf maps the whole zone) */
+  int32_t* ref_of;      /* NULL, or device [ncells] out: the reference's index for a
+                           mapped cell, -1 for an integrated one */
+} chem_refmap;
+
 /* Integrator options; pass NULL for the defaults in brackets. */
 typedef struct chem_options {
   int32_t method;     /* 0 ROS4 [0], 1 Rodas3, 2 Seulex-family extrapolated linearly implicit
@@ -86,11 +110,15 @@ typedef struct chem_options {
   int32_t use_graph;  /* 1: launch the reset + integrate sequence as a cached hipGraph [0] */
   uint64_t* phase_cycles; /* NULL [NULL], or device [ncells][8] shader-clock cycles per cell:
                              Jacobian pass, forming M, LU, stage f, solves, total, and the
-                             reaction and species parts of the Jacobian pass */
+                             reaction and species parts of the Jacobian pass; with method 2
+                             slots 6 and 7 count the LU factorisations and the linearly
+                             implicit Euler substeps instead */
   /* Ablation switches of section 2.3 (N <= 64; they select the instrumented kernel): */
   int32_t jac_mode;   /* 0 analytic Jacobian [0], 1 one-sided finite differences, column j
                          from f(y + d_j e_j), d_j = sqrt(eps) max(|y_j|, 1e-10) */
   int32_t lu_pivot;   /* 0 partial pivoting [0], 1 no pivoting (rows in natural order) */
+  const chem_refmap* refmap; /* NULL [NULL], or reference-cell mapping for this call
+                                (chem_integrate only; the adjoint rejects it) */
 } chem_options;
 
 /* Validates (element balance is not required; indices, cp > 0 on

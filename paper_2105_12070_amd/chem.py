@@ -33,23 +33,38 @@ class _Desc(C.Structure):
                 ("troe", C.c_void_p), ("low", C.c_void_p)]
 
 
+class RefMap(C.Structure):
+    """chem_refmap (reference-cell mapping of low-reactivity cells); see include/chem.h."""
+    _fields_ = [("weight", C.c_void_p), ("z0", C.c_double), ("z_max", C.c_double), ("dT", C.c_double),
+                ("ref_of", C.c_void_p)]
+
+    def __init__(self, weight, z0=0.0, z_max=0.0, dT=0.0, ref_of=None):
+        """weight: float64 CUDA tensor [K]; ref_of: None or an int32 CUDA tensor [ncells] (output)."""
+        _dev(weight, torch.float64, "weight")
+        _dev(ref_of, torch.int32, "ref_of")
+        super().__init__(weight.data_ptr(), z0, z_max, dT, ref_of.data_ptr() if ref_of is not None else None)
+        self._keep = (weight, ref_of)
+
+
 class Options(C.Structure):
     """chem_options; see include/chem.h for the meaning and defaults."""
     _fields_ = [("method", C.c_int32), ("max_steps", C.c_int32), ("fac_safe", C.c_double),
                 ("fac_min", C.c_double), ("fac_max", C.c_double), ("h_min", C.c_double),
                 ("persistent", C.c_int32), ("waves_per_block", C.c_int32), ("grid_mult", C.c_int32),
                 ("cost_order", C.c_int32), ("use_graph", C.c_int32), ("phase_cycles", C.c_void_p),
-                ("jac_mode", C.c_int32), ("lu_pivot", C.c_int32)]
+                ("jac_mode", C.c_int32), ("lu_pivot", C.c_int32), ("refmap", C.POINTER(RefMap))]
 
     def __init__(self, method=0, max_steps=100000, fac_safe=0.9, fac_min=0.2, fac_max=6.0, h_min=1e-20,
                  persistent=-1, waves_per_block=0, grid_mult=0, cost_order=0, use_graph=0, phase_cycles=None,
-                 jac_mode=0, lu_pivot=0):
+                 jac_mode=0, lu_pivot=0, refmap=None):
         """phase_cycles: None or an int64 CUDA tensor [ncells, 8] (per-phase shader cycles);
-        jac_mode 1 / lu_pivot 1 select the finite-difference Jacobian / unpivoted LU (ablation)."""
+        jac_mode 1 / lu_pivot 1 select the finite-difference Jacobian / unpivoted LU (ablation);
+        refmap: None or a RefMap."""
         ptr = phase_cycles.data_ptr() if phase_cycles is not None else None
+        rp = C.pointer(refmap) if refmap is not None else None
         super().__init__(method, max_steps, fac_safe, fac_min, fac_max, h_min, persistent, waves_per_block,
-                         grid_mult, cost_order, use_graph, ptr, jac_mode, lu_pivot)
-        self._keep = phase_cycles
+                         grid_mult, cost_order, use_graph, ptr, jac_mode, lu_pivot, rp)
+        self._keep = (phase_cycles, refmap)
 
 
 _lib = None

@@ -51,7 +51,8 @@ __global__ __launch_bounds__(max_threads<NP>()) void k_integrate(IntArgs a) {
   } else {
     idx = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
   }
-  while (idx < a.ncells) {
+  const int64_t lim = a.nactive ? (int64_t)*a.nactive : a.ncells;
+  while (idx < lim) {
     const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
     integrate_cell<NP, PROF>(m, w, a, c);
     if (!a.queue) break;
@@ -77,7 +78,8 @@ __global__ __launch_bounds__(max_threads<NP>()) void k_integrate_sx(IntArgs a) {
   } else {
     idx = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
   }
-  while (idx < a.ncells) {
+  const int64_t lim = a.nactive ? (int64_t)*a.nactive : a.ncells;
+  while (idx < lim) {
     const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
     integrate_cell_sx<NP, PROF>(m, w, a, c);
     if (!a.queue) break;
@@ -161,7 +163,8 @@ __global__ __launch_bounds__(WG, 2) void k_integrate_wg(IntArgs a, WgTerms tl, d
   __syncthreads();
   int64_t idx = w.flag[3];
   __syncthreads();
-  while (idx < a.ncells) {
+  const int64_t lim = a.nactive ? (int64_t)*a.nactive : a.ncells;
+  while (idx < lim) {
     const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
     wg_integrate_cell<PROF>(m, w, tl, Sx, Mx, NP, a, c);
     if (threadIdx.x == 0) w.flag[3] = atomicAdd(a.queue, 1);
@@ -245,19 +248,23 @@ __device__ __forceinline__ int cost_bucket(int32_t s) {
   return 31 - __clz(v);
 }
 
-__global__ void k_order_count(const int32_t* steps, int64_t n, int* cnt) {
+// A cell enters the queue unless excl[i] >= 0 (a mapped cell); with steps
+// NULL every cell falls in one bucket (plain compaction).
+__device__ __forceinline__ bool queued(const int32_t* excl, int64_t i) { return !excl || excl[i] < 0; }
+
+__global__ void k_order_count(const int32_t* steps, const int32_t* excl, int64_t n, int* cnt) {
   __shared__ int loc[NBUCKET];
   if (threadIdx.x < NBUCKET) loc[threadIdx.x] = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&loc[cost_bucket(steps[i])], 1);
+  if (i < n && queued(excl, i)) atomicAdd(&loc[steps ? cost_bucket(steps[i]) : 0], 1);
   __syncthreads();
   if (threadIdx.x < NBUCKET && loc[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], loc[threadIdx.x]);
 }
 
-// cnt[0..31] counts (cleared by the previous use), cnt[32..63] bucket cursors
+// cnt[0..31] counts, cnt[32..63] bucket cursors, cnt[64] the queue length
 __global__ void k_order_clear(int* cnt) {
-  if (threadIdx.x < 2 * NBUCKET) cnt[threadIdx.x] = 0;
+  if (threadIdx.x <= 2 * NBUCKET) cnt[threadIdx.x] = 0;
 }
 
 __global__ void k_order_scan(int* cnt) {
@@ -267,23 +274,82 @@ __global__ void k_order_scan(int* cnt) {
       cnt[NBUCKET + b] = off;
       off += cnt[b];
     }
+    cnt[2 * NBUCKET] = off;
   }
 }
 
-__global__ void k_order_scatter(const int32_t* steps, int64_t n, int* cnt, int32_t* order) {
+__global__ void k_order_scatter(const int32_t* steps, const int32_t* excl, int64_t n, int* cnt, int32_t* order) {
   __shared__ int loc[NBUCKET], base[NBUCKET];
   if (threadIdx.x < NBUCKET) loc[threadIdx.x] = 0;
   __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < n && queued(excl, i);
   int b = 0, r = 0;
-  if (i < n) {
-    b = cost_bucket(steps[i]);
+  if (in) {
+    b = steps ? cost_bucket(steps[i]) : 0;
     r = atomicAdd(&loc[b], 1);
   }
   __syncthreads();
   if (threadIdx.x < NBUCKET && loc[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cnt[NBUCKET + threadIdx.x], loc[threadIdx.x]);
   __syncthreads();
-  if (i < n) order[base[b] + r] = (int32_t)i;
+  if (in) order[base[b] + r] = (int32_t)i;
+}
+
+// ------------------------------------------------ reference-cell mapping (section 2.2)
+// Low-reactivity zone: z = z0 + sum_k w_k Y_k <= z_max (species in index
+// order, fused multiply-adds).  The reference is the zone cell of lowest
+// index; zone cells within dT of its temperature take its increment instead of
+// being integrated.  rm[0] holds the reference index (~0 if the zone is
+// empty), rm[1..N] the reference's initial state.
+__global__ void k_refmap_init(unsigned long long* rm) {
+  if (threadIdx.x == 0) rm[0] = ~0ull;
+}
+
+__global__ void k_refmap_zone(const double* st, int64_t ld, int64_t n, int K, const double* wt, double z0,
+                              double zmax, int32_t* ref_of, unsigned long long* rm) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool zone = false;
+  if (c < n) {
+    double z = z0;
+    for (int k = 0; k < K; ++k) z = __builtin_fma(wt[k], st[(int64_t)(k + 1) * ld + c], z);
+    zone = z <= zmax;
+    ref_of[c] = zone ? -2 : -1;
+  }
+  // lanes hold consecutive cells: the lowest zone lane is the wave's candidate
+  const unsigned long long mask = __ballot(zone);
+  if (mask && lane_id() == __ffsll((long long)mask) - 1) atomicMin(rm, (unsigned long long)c);
+}
+
+__global__ void k_refmap_mark(double* st, int64_t ld, int64_t n, int N, double dT, int32_t* ref_of,
+                              unsigned long long* rm) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const unsigned long long r = rm[0];
+  const bool have = r != ~0ull;
+  const bool mapped = have && (unsigned long long)c != r && ref_of[c] == -2 && fabs(st[c] - st[r]) <= dT;
+  ref_of[c] = mapped ? (int32_t)r : -1;
+  if (have && (unsigned long long)c == r) {
+    double* y0 = (double*)(rm + 1);
+    for (int i = 0; i < N; ++i) y0[i] = st[(int64_t)i * ld + c];
+  }
+}
+
+__global__ void k_refmap_apply(double* st, int64_t ld, int64_t n, int N, const int32_t* ref_of,
+                               const unsigned long long* rm, double* h, int32_t* steps, int32_t* rejects,
+                               int32_t* status) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int32_t r = ref_of[c];
+  if (r < 0) return;
+  const double* y0 = (const double*)(rm + 1);
+  for (int i = 0; i < N; ++i) {
+    const int64_t o = (int64_t)i * ld;
+    st[o + c] = st[o + c] + (st[o + r] - y0[i]);
+  }
+  h[c] = h[r];
+  if (steps) steps[c] = 0;
+  if (rejects) rejects[c] = 0;
+  if (status) status[c] = status[r];
 }
 
 }  // namespace
@@ -325,7 +391,11 @@ struct chem_mech {
   int* queue = nullptr;     // device work cursor
   int32_t* order = nullptr; // device cost order of the queue
   int64_t order_cap = 0;
-  int* order_cnt = nullptr; // device bucket counters [64]
+  int* order_cnt = nullptr; // device bucket counters and cursors [64], queue length [1]
+  // reference-cell mapping: reference index + its initial state, zone flags
+  unsigned long long* rm_buf = nullptr;
+  int32_t* rm_flags = nullptr;
+  int64_t rm_cap = 0;
   Variant tuned;
   bool has_tuned = false;
   // cached graph of the persistent launch
@@ -487,13 +557,37 @@ int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStrea
   });
 }
 
-// Launches the cost ordering of ncells cells from steps into m->order.
-int launch_order(chem_mech* m, const int32_t* steps, int64_t ncells, hipStream_t s) {
+// Builds the queue in m->order: cells with excl[i] >= 0 left out (if excl is
+// given), the rest by descending cost bucket of steps (if given); the queue
+// length goes to m->order_cnt[2 NBUCKET].
+int launch_order(chem_mech* m, const int32_t* steps, const int32_t* excl, int64_t ncells, hipStream_t s) {
   const int nb = (int)((ncells + 255) / 256);
-  hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(64), 0, s, m->order_cnt);
-  hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(256), 0, s, steps, ncells, m->order_cnt);
+  hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(128), 0, s, m->order_cnt);
+  hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(256), 0, s, steps, excl, ncells, m->order_cnt);
   hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, m->order_cnt);
-  hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, s, steps, ncells, m->order_cnt, m->order);
+  hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, s, steps, excl, ncells, m->order_cnt, m->order);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+// Zone test, reference choice and marking of the mapped cells (before the
+// integration), and the increments of the mapped cells (after it).
+int launch_refmap_mark(chem_mech* m, const chem_refmap& rm, int32_t* ref_of, double* state, int64_t ld,
+                       int64_t ncells, hipStream_t s) {
+  const int nb = (int)((ncells + 255) / 256);
+  hipLaunchKernelGGL(k_refmap_init, dim3(1), dim3(64), 0, s, m->rm_buf);
+  hipLaunchKernelGGL(k_refmap_zone, dim3(nb), dim3(256), 0, s, state, ld, ncells, m->d.K, rm.weight, rm.z0,
+                     rm.z_max, ref_of, m->rm_buf);
+  hipLaunchKernelGGL(k_refmap_mark, dim3(nb), dim3(256), 0, s, state, ld, ncells, m->d.N, rm.dT, ref_of, m->rm_buf);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int launch_refmap_apply(chem_mech* m, const int32_t* ref_of, double* state, int64_t ld, int64_t ncells, double* h,
+                        int32_t* steps, int32_t* rejects, int32_t* status, hipStream_t s) {
+  const int nb = (int)((ncells + 255) / 256);
+  hipLaunchKernelGGL(k_refmap_apply, dim3(nb), dim3(256), 0, s, state, ld, ncells, m->d.N, ref_of, m->rm_buf, h,
+                     steps, rejects, status);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -784,6 +878,8 @@ void chem_free_mechanism(chem_mech* m) {
   hipFree(m->adj_ws);
   hipFree(m->order);
   hipFree(m->order_cnt);
+  hipFree(m->rm_buf);
+  hipFree(m->rm_flags);
   hipFree(m->wg_gptr);
   hipFree(m->wg_grp);
   hipFree(m->wg_term);
@@ -880,7 +976,24 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
   const Variant v = pick_variant(m, opt, ncells);
   hipStream_t s = (hipStream_t)stream;
   const bool ordered = opt && opt->cost_order && steps && v.persistent;
-  if (ordered && m->order_cap < ncells) {
+  const chem_refmap* rmp = opt ? opt->refmap : nullptr;
+  if (rmp) {
+    if ((m->d.K > 0 && !rmp->weight) || std::isnan(rmp->z0) || std::isnan(rmp->z_max) || !(rmp->dT >= 0.0))
+      return fail(CHEM_EINVAL, "reference mapping needs a weight array, non-NaN z0 and z_max, and dT >= 0");
+    if (!m->rm_buf && hipMalloc(&m->rm_buf, sizeof(unsigned long long) * (m->d.N + 1)) != hipSuccess)
+      return fail(CHEM_ENOMEM, "reference-mapping buffer allocation failed");
+    if (!rmp->ref_of && m->rm_cap < ncells) {
+      hipFree(m->rm_flags);
+      m->rm_flags = nullptr;
+      m->rm_cap = 0;
+      if (hipMalloc(&m->rm_flags, sizeof(int32_t) * ncells) != hipSuccess)
+        return fail(CHEM_ENOMEM, "reference-mapping flag allocation failed");
+      m->rm_cap = ncells;
+    }
+  }
+  int32_t* ref_of = rmp ? (rmp->ref_of ? rmp->ref_of : m->rm_flags) : nullptr;
+  const bool queued = ordered || rmp;
+  if (queued && m->order_cap < ncells) {
     hipFree(m->order);
     m->order = nullptr;
     m->order_cap = 0;
@@ -888,28 +1001,33 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
       return fail(CHEM_ENOMEM, "cost-order buffer allocation failed");
     m->order_cap = ncells;
   }
-  if (ordered && !m->order_cnt) {
-    if (hipMalloc(&m->order_cnt, sizeof(int) * 2 * NBUCKET) != hipSuccess)
+  if (queued && !m->order_cnt) {
+    if (hipMalloc(&m->order_cnt, sizeof(int) * (2 * NBUCKET + 4)) != hipSuccess)
       return fail(CHEM_ENOMEM, "cost-order counter allocation failed");
   }
-  if (ordered) a.order = m->order;
+  if (queued) a.order = m->order;
+  if (rmp) a.nactive = m->order_cnt + 2 * NBUCKET;
   if (m->wg) {
     const int rc = ensure_wg_scratch(m, wg_grid(m, ncells), 2);
     if (rc) return rc;
   }
   auto launch_all = [&](hipStream_t st) -> int {
-    if (ordered) {
-      const int rc = launch_order(m, steps, ncells, st);
-      if (rc) return rc;
-    }
-    return launch_integrate(m, a, v, st);
+    int rc = 0;
+    if (rmp && (rc = launch_refmap_mark(m, *rmp, ref_of, state, ld, ncells, st))) return rc;
+    if (queued && (rc = launch_order(m, ordered ? steps : nullptr, ref_of, ncells, st))) return rc;
+    if ((rc = launch_integrate(m, a, v, st))) return rc;
+    if (rmp) rc = launch_refmap_apply(m, ref_of, state, ld, ncells, h, steps, rejects, status, st);
+    return rc;
   };
   if (opt && opt->use_graph && v.persistent) {
     GraphKey key;
     key.v = {(uintptr_t)state, (uintptr_t)h, (uintptr_t)ncells, (uintptr_t)ld, (uintptr_t)steps,
              (uintptr_t)rejects, (uintptr_t)status, (uintptr_t)s, (uintptr_t)v.wpb, (uintptr_t)v.grid_mult,
-             (uintptr_t)ordered, (uintptr_t)m->order, (uintptr_t)m->wg_scr};
-    double dv[7] = {p, dt, rtol, atol, (double)(opt ? opt->method : 0), (double)a.jac_fd, (double)a.lu_nopiv};
+             (uintptr_t)ordered, (uintptr_t)m->order, (uintptr_t)m->wg_scr, (uintptr_t)m->order_cnt,
+             (uintptr_t)(rmp != nullptr), (uintptr_t)(rmp ? rmp->weight : nullptr), (uintptr_t)ref_of,
+             (uintptr_t)m->rm_buf};
+    double dv[10] = {p, dt, rtol, atol, (double)(opt ? opt->method : 0), (double)a.jac_fd, (double)a.lu_nopiv,
+                     rmp ? rmp->z0 : 0.0, rmp ? rmp->z_max : 0.0, rmp ? rmp->dT : 0.0};
     for (double x : dv) {
       uint64_t u;
       std::memcpy(&u, &x, 8);

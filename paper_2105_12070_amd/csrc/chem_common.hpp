@@ -84,6 +84,7 @@ struct IntArgs {
   int32_t* status;
   int* queue;               // persistent work cursor (NULL: one cell per wave slot)
   const int32_t* order;     // optional cell order for the queue
+  const int* nactive;       // optional device count of queue entries (default ncells)
   int cell_doubles;         // per-wave LDS workspace in doubles
   // adjoint tape (NULL in the forward integrator)
   double* tape_h;           // [ncells][max_tape]

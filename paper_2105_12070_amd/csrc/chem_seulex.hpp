@@ -42,6 +42,7 @@ __device__ void integrate_cell_sx(const MechView& m, const CellWs& w, const IntA
   const double hin = a.h[c];
   double hprop = (__builtin_isfinite(hin) && hin > 0.0) ? fmin(hin, dt) : dt;
   int status = ST_OK, steps = 0, rejects = 0, attempts = 0;
+  int nlu = 0, nsub = 0;  // work counters of the instrumented kernel
   const bool bad = lane < N && (!__builtin_isfinite(y) || (lane == 0 && !(y > 0.0)));
   if (ballot(bad)) status = ST_NONFINITE;
   double t = 0.0;
@@ -86,6 +87,10 @@ __device__ void integrate_cell_sx(const MechView& m, const CellWs& w, const IntA
         }
         const int src = permute_rows<NP>(row, N, lane, mystep, myrdiag, w.slot);
         pf.stop(2);
+        if (PROF) {
+          ++nlu;
+          nsub += nj;
+        }
         double yc = y;
 #pragma clang loop unroll(disable)
         for (int mm = 0; mm < nj; ++mm) {
@@ -184,6 +189,8 @@ __device__ void integrate_cell_sx(const MechView& m, const CellWs& w, const IntA
     for (int i = 0; i < 8; ++i)
       if (lane == i) v = pf.c[i];
     if (lane == 5) v = __builtin_readcyclecounter() - t_begin;
+    if (lane == 6) v = (unsigned long long)nlu;
+    if (lane == 7) v = (unsigned long long)nsub;
     a.prof[c * 8 + lane] = v;
   }
 }

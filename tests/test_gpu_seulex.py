@@ -83,3 +83,23 @@ def test_seulex_unsupported_combinations(chem):
                                options=chem.Options(method=2))
     with pytest.raises(chem.ChemError):
         chem.integrate(m, s, h, w.p_pa, w.dt, w.rtol, w.atol, options=chem.Options(method=3))
+
+
+def test_seulex_instrumented_counts(chem):
+    """The instrumented kernel takes the same steps as the plain one and counts
+    its factorisations (2..6 columns per attempt) and substeps (n_j = j)."""
+    w = WORKLOADS["c2_54sp"]
+    mech = w.mechanism()
+    st0 = w.states(mech, 64)
+    a = run(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol)
+    pc = torch.zeros((64, 8), dtype=torch.int64, device=DEV)
+    b = run(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, phase_cycles=pc)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    pcn = pc.cpu().numpy()
+    att = a[2] + a[3]
+    nlu, nsub = pcn[:, 6], pcn[:, 7]
+    assert np.all(nlu >= 2 * att) and np.all(nlu <= 6 * att)
+    # columns 1..k take 1..k substeps: k(k+1)/2 substeps for k factorisations
+    assert np.all(nsub >= 1.5 * nlu) and np.all(nsub <= 3.5 * nlu)
+    print(f"[seulex counts] LU per attempt {nlu.sum() / att.sum():.2f}, substeps per LU {nsub.sum() / nlu.sum():.2f}")
