@@ -38,6 +38,8 @@ struct WgTerms {
 
 // Per-workgroup LDS workspace (beyond the staged mechanism blob); NP = N
 // rounded up to a multiple of 16.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 struct WgWs {
   double* C;     // [NP] concentrations, C[K] = 1
   double* g;     // [NP] g/RT
@@ -434,14 +436,15 @@ __device__ inline void wg_panel(const WgWs& w, int p0, int NP, int lane) {
     const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
     const unsigned mh = wave_max_u32(best < 0.0 ? 0u : hi);
     const unsigned ml = wave_max_u32((best >= 0.0 && hi == mh) ? lo : 0u);
-    int cand = (best >= 0.0 && hi == mh && lo == ml) ? brel : (1 << 20);
-    cand = min(cand, __shfl_xor(cand, 32));
-    cand = min(cand, __shfl_xor(cand, 16));
-    cand = min(cand, __shfl_xor(cand, 8));
-    cand = min(cand, __shfl_xor(cand, 4));
-    cand = min(cand, __shfl_xor(cand, 2));
-    cand = min(cand, __shfl_xor(cand, 1));
-    int pr = uniform_int(cand);
+    // first row holding the maximum: the lowest slot with a holder, then the
+    // lowest lane in it (one ballot per slot)
+    const bool holder = best >= 0.0 && hi == mh && lo == ml;
+    int pr = kk;
+#pragma unroll
+    for (int sl = NS - 1; sl >= 0; --sl) {
+      const unsigned long long bm = ballot(holder && brel / WAVE == sl);
+      if (bm) pr = sl * WAVE + (int)__builtin_ctzll(bm);
+    }
     pr = pr < nrow ? pr : kk;
     const int lp = pr & (WAVE - 1), sp = pr / WAVE;
     double b[WNB];
@@ -463,7 +466,7 @@ __device__ inline void wg_panel(const WgWs& w, int p0, int NP, int lane) {
         P[0][c] = lane == kk ? b[c] : P[0][c];
       }
     }
-    const double rp = sing ? 0.0 : 1.0 / pv;
+    const double rp = sing ? 0.0 : recip(pv);
     if (lane == 0) {
       w.piv[p0 + kk] = (sing ? kk : pr) + p0;
       w.rdg[p0 + kk] = rp;
@@ -637,51 +640,43 @@ __device__ inline int wg_lu(const WgWs& w, double* Mx, int NP, Prof<PROF>* pf = 
     for (int idx = t; idx < nrow * WNB; idx += WG) Mx[(size_t)(p0 + idx / WNB) * NP + p0 + (idx % WNB)] = w.Pn[idx];
     __syncthreads();
     if (PROF) pf->add(7, tp);
-    // trailing update: rows and columns >= p0 + 16, 4 x 4 blocks per thread
-    const int m0 = p0 + WNB, mt = NP - m0;
-    if (mt > 0) {
-      const int nb = mt / 4;
-      // two blocks per pass so that 32 loads are in flight together
+    // trailing update A22 -= L21 U12 on FP64 MFMA (v_mfma_f64_16x16x4f64):
+    // 16 x 16 output tiles; wave wv takes tile rows wv, wv + 4, ... and keeps
+    // the row's L21 operand (16 x 16, negated) in registers across its tile
+    // columns, two of which are in flight.  Lane layouts of the instruction:
+    // lane l holds A[l % 16][l / 16], B[l / 16][l % 16] and D[l / 16 + 4 v][l % 16].
+    const int m0 = p0 + WNB, nt = (NP - m0) / 16;
+    const int li = lane & 15, lk = lane >> 4;
 #pragma clang loop unroll(disable)
-      for (int bidx = t; bidx < nb * nb; bidx += 2 * WG) {
-        const bool two = bidx + WG < nb * nb;
-        int i0[2], j0[2];
+    for (int bi = uniform_int(wv); bi < nt; bi += WG / WAVE) {
+      const int i0 = m0 + 16 * bi;
+      double am[4];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int bb = (u == 0 || two) ? bidx + u * WG : bidx;
-          const int bi = bb / nb;
-          i0[u] = m0 + 4 * bi;
-          j0[u] = m0 + 4 * (bb - bi * nb);
-        }
-        double a[2][4][4];
+      for (int s4 = 0; s4 < 4; ++s4) am[s4] = -w.Pn[(i0 - p0 + li) * WNB + 4 * s4 + lk];
+      double* rowp = Mx + (size_t)(i0 + lk) * NP + m0 + li;
+      const double* ub = w.Ub + (size_t)lk * NP + m0 + li;
+#pragma clang loop unroll(disable)
+      for (int bj = 0; bj < nt; bj += 2) {
+        const bool two = bj + 1 < nt;
+        double* r0 = rowp + 16 * bj;
+        const double* u0 = ub + 16 * bj;
+        dbl4 c0, c1;
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
+        for (int v = 0; v < 4; ++v) c0[v] = r0[(size_t)4 * v * NP];
+        if (two) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int c = 0; c < 4; ++c) a[u][r][c] = Mx[(size_t)(i0[u] + r) * NP + j0[u] + c];
-#pragma unroll
-        for (int q = 0; q < WNB; ++q) {
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            double lq[4], uq[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) lq[r] = w.Pn[(i0[u] + r - p0) * WNB + q];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) uq[c] = w.Ub[q * NP + j0[u] + c];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-              for (int c = 0; c < 4; ++c) a[u][r][c] = fma(-lq[r], uq[c], a[u][r][c]);
-          }
+          for (int v = 0; v < 4; ++v) c1[v] = r0[(size_t)4 * v * NP + 16];
         }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          if (u == 1 && !two) break;
+        for (int s4 = 0; s4 < 4; ++s4) {
+          c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(am[s4], u0[(size_t)4 * s4 * NP], c0, 0, 0, 0);
+          if (two) c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(am[s4], u0[(size_t)4 * s4 * NP + 16], c1, 0, 0, 0);
+        }
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
+        for (int v = 0; v < 4; ++v) r0[(size_t)4 * v * NP] = c0[v];
+        if (two) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) Mx[(size_t)(i0[u] + r) * NP + j0[u] + c] = a[u][r][c];
+          for (int v = 0; v < 4; ++v) r0[(size_t)4 * v * NP + 16] = c1[v];
         }
       }
     }
