@@ -361,58 +361,83 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
   double om = 0.0, dwdT = 0.0, adense = 0.0;
   if (isSp) {
     const int k = lane - 1;
-    const int e0 = m.cptr[k], e1 = m.cptr[k + 1];
-    // the next entry's table words are loaded one iteration ahead
-    uint32_t vnext = e0 < e1 ? m.cent[e0] : 0u;
-    uint64_t snext = e0 < e1 ? m.sp[vnext >> 8] : 0ull;
+    const int e1 = m.cptr[k + 1];
+    int e = m.cptr[k];
+    // entries two at a time (the second masked off past the end, so the
+    // iteration has no branch on it); the next pair's table words are loaded
+    // one iteration ahead.  Sums and LDS adds keep the entries' order.
+    uint32_t va = e < e1 ? m.cent[e] : 0u, vb = e + 1 < e1 ? m.cent[e + 1] : 0u;
+    uint64_t sa = e < e1 ? m.sp[va >> 8] : 0ull, sb = e < e1 ? m.sp[vb >> 8] : 0ull;
 #pragma clang loop unroll(disable)
-    for (int e = e0; e < e1; ++e) {
-      const uint32_t v = vnext;
-      const uint64_t sw = snext;
-      if (e + 1 < e1) {
-        vnext = m.cent[e + 1];
-        snext = m.sp[vnext >> 8];
+    for (; e < e1; e += 2) {
+      const bool hb = e + 1 < e1;
+      const uint32_t v0 = va, v1 = vb;
+      const Slots s0 = unpack(sa), s1 = unpack(sb);
+      va = e + 2 < e1 ? m.cent[e + 2] : 0u;
+      vb = e + 3 < e1 ? m.cent[e + 3] : 0u;
+      const int r0 = (int)(v0 >> 8), r1 = (int)(v1 >> 8);
+      const double nu0 = (double)(int8_t)(v0 & 0xFF), nu1 = hb ? (double)(int8_t)(v1 & 0xFF) : 0.0;
+      const double a0c0 = w.C[s0.r0], a0c1 = w.C[s0.r1], a0c2 = w.C[s0.r2];
+      const double a0d0 = w.C[s0.p0], a0d1 = w.C[s0.p1], a0d2 = w.C[s0.p2];
+      const double a1c0 = w.C[s1.r0], a1c1 = w.C[s1.r1], a1c2 = w.C[s1.r2];
+      const double a1d0 = w.C[s1.p0], a1d1 = w.C[s1.p1], a1d2 = w.C[s1.p2];
+      const double kf0 = w.rk[r0], kr0 = w.rkr[r0], dt0 = w.rdt[r0];
+      const double kf1 = w.rk[r1], kr1 = w.rkr[r1], dt1 = w.rdt[r1];
+      sa = m.sp[va >> 8];
+      sb = m.sp[vb >> 8];
+      om += nu0 * (kf0 * a0c0 * a0c1 * a0c2 - kr0 * a0d0 * a0d1 * a0d2);
+      dwdT += nu0 * dt0;
+      {
+        const double a = nu0 * kf0, bb = -nu0 * kr0;
+        atomicAdd(Jr + 1 + s0.r0, a * a0c1 * a0c2);
+        atomicAdd(Jr + 1 + s0.r1, a * a0c0 * a0c2);
+        atomicAdd(Jr + 1 + s0.r2, a * a0c0 * a0c1);
+        atomicAdd(Jr + 1 + s0.p0, bb * a0d1 * a0d2);
+        atomicAdd(Jr + 1 + s0.p1, bb * a0d0 * a0d2);
+        atomicAdd(Jr + 1 + s0.p2, bb * a0d0 * a0d1);
       }
-      const int r = (int)(v >> 8);
-      const double nu = (double)(int8_t)(v & 0xFF);
-      const Slots s = unpack(sw);
-      const double c0 = w.C[s.r0], c1 = w.C[s.r1], c2 = w.C[s.r2];
-      const double d0 = w.C[s.p0], d1 = w.C[s.p1], d2 = w.C[s.p2];
-      const double kf = w.rk[r], kr = w.rkr[r];
-      om += nu * (kf * c0 * c1 * c2 - kr * d0 * d1 * d2);
-      dwdT += nu * w.rdt[r];
-      const double a = nu * kf, bb = -nu * kr;
-      atomicAdd(Jr + 1 + s.r0, a * c1 * c2);
-      atomicAdd(Jr + 1 + s.r1, a * c0 * c2);
-      atomicAdd(Jr + 1 + s.r2, a * c0 * c1);
-      atomicAdd(Jr + 1 + s.p0, bb * d1 * d2);
-      atomicAdd(Jr + 1 + s.p1, bb * d0 * d2);
-      atomicAdd(Jr + 1 + s.p2, bb * d0 * d1);
-      if (r >= m.d.R0) {
-        const double dm = nu * w.rdm[r];
+      if (r0 >= m.d.R0) {
+        const double dm = nu0 * w.rdm[r0];
         adense += dm;
-        const int e1 = m.tbp[r - m.d.R0 + 1];
+        const int t1 = m.tbp[r0 - m.d.R0 + 1];
 #pragma clang loop unroll(disable)
-        for (int e = m.tbp[r - m.d.R0]; e < e1; ++e) atomicAdd(Jr + 1 + m.tbs[e], dm * m.tbd[e]);
+        for (int q = m.tbp[r0 - m.d.R0]; q < t1; ++q) atomicAdd(Jr + 1 + m.tbs[q], dm * m.tbd[q]);
+      }
+      if (hb) {
+        om += nu1 * (kf1 * a1c0 * a1c1 * a1c2 - kr1 * a1d0 * a1d1 * a1d2);
+        dwdT += nu1 * dt1;
+        const double a = nu1 * kf1, bb = -nu1 * kr1;
+        atomicAdd(Jr + 1 + s1.r0, a * a1c1 * a1c2);
+        atomicAdd(Jr + 1 + s1.r1, a * a1c0 * a1c2);
+        atomicAdd(Jr + 1 + s1.r2, a * a1c0 * a1c1);
+        atomicAdd(Jr + 1 + s1.p0, bb * a1d1 * a1d2);
+        atomicAdd(Jr + 1 + s1.p1, bb * a1d0 * a1d2);
+        atomicAdd(Jr + 1 + s1.p2, bb * a1d0 * a1d1);
+        if (r1 >= m.d.R0) {
+          const double dm = nu1 * w.rdm[r1];
+          adense += dm;
+          const int t1 = m.tbp[r1 - m.d.R0 + 1];
+#pragma clang loop unroll(disable)
+          for (int q = m.tbp[r1 - m.d.R0]; q < t1; ++q) atomicAdd(Jr + 1 + m.tbs[q], dm * m.tbd[q]);
+        }
       }
     }
   }
   wsync();
   // dense transform of the lane's row: rank-1 density term and W scaling
+  // (uniform loop bounds: no per-column branches; padding columns set to 0)
   double fk = 0.0;
   if (isSp) {
     const int k = lane - 1;
     const double Wk = m.W[k];
     double sk = 0.0;
-#pragma unroll
-    for (int j = 1; j < NP; ++j) {
-      const double v = j < N ? Jr[j] + adense : 0.0;
-      row[j] = v;
-      sk += (j < N ? w.C[j - 1] : 0.0) * v;
-    }
+#pragma clang loop unroll_count(4)
+    for (int j = 1; j < N; ++j) sk += w.C[j - 1] * (Jr[j] + adense);
     const double gam = Wk * x.Wbar * x.iRho * (om - sk);
-#pragma unroll
-    for (int j = 1; j < NP; ++j) Jr[j] = j < N ? m.iW[j - 1] * (Wk * row[j] + gam) : 0.0;
+#pragma clang loop unroll_count(4)
+    for (int j = 1; j < N; ++j) Jr[j] = m.iW[j - 1] * (Wk * (Jr[j] + adense) + gam);
+#pragma clang loop unroll(disable)
+    for (int j = N; j < NP; ++j) Jr[j] = 0.0;
     Jr[0] = Wk * x.iRho * (dwdT - sk * x.iT + om * x.iT);
     fk = Wk * om * x.iRho;
     // mass-specific enthalpy for the T row (g/RT is no longer needed)
@@ -615,9 +640,12 @@ __device__ inline bool form_matrix(const CellWs& w, int N, int S, int lane, doub
     const double jd = Jr[lane];
     Jr[lane] = jd - d;
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // every load is in the row (j < NP < S) and taken unconditionally; the
+    // padding columns are selected away, so the unrolled loop has no branches
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-      row[j] = j < N ? -Jr[j] : 0.0;
+      const double v = Jr[j];
+      row[j] = j < N ? -v : 0.0;
       chk += row[j];
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
