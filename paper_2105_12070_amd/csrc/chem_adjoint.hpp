@@ -319,14 +319,14 @@ __device__ S vjp_f(const MechView& m, const AdjMech& am, const AdjView<S>& v, do
 template <int NP>
 __device__ inline double lu_solve_T(const double* F, int N, int S, int lane, int mystep, double myrdiag, double b) {
   // rows >= N of F are not factors: those steps are skipped (uniform branch);
-  // padding lanes read column 0 and are masked
+  // padding lanes read column 0 and are masked.  The masks act on the
+  // multipliers, off the chain through b (adding -0 leaves b as it is).
   const int col = lane < N ? lane : 0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     if (k < N) {
       const double zk = readlane(b * myrdiag, k);
-      const double v = fma(-F[k * S + col], zk, b);
-      b = (lane > k && lane < N) ? v : b;
+      b = fma((lane > k && lane < N) ? -F[k * S + col] : -0.0, zk, b);
     }
   }
   b *= myrdiag;
@@ -334,8 +334,7 @@ __device__ inline double lu_solve_T(const double* F, int N, int S, int lane, int
   for (int k = NP - 1; k >= 0; --k) {
     if (k < N) {
       const double vk = readlane(b, k);
-      const double v = fma(-F[k * S + col], vk, b);
-      b = lane < k ? v : b;
+      b = fma(lane < k ? -F[k * S + col] : -0.0, vk, b);
     }
   }
   return __shfl(b, mystep);

@@ -613,17 +613,18 @@ __device__ inline double lu_solve(const double (&row)[NP], int N, int lane, int 
   // padding lanes carry b = 0 and zero rows, so all NP steps run unconditionally
   (void)N;
   b = __shfl(b, src);
+  // the triangle masks act on the multipliers, which do not depend on b, so
+  // each step's dependency chain is one broadcast and one FMA (adding -0
+  // leaves b as it is)
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const double yk = readlane(b, k);
-    const double v = fma(-row[k], yk, b);
-    b = lane > k ? v : b;
+    b = fma(lane > k ? -row[k] : -0.0, yk, b);
   }
 #pragma unroll
   for (int k = NP - 1; k >= 0; --k) {
     const double xk = readlane(b * myrdiag, k);
-    const double v = fma(-row[k], xk, b);
-    b = lane < k ? v : b;
+    b = fma(lane < k ? -row[k] : -0.0, xk, b);
   }
   return b * myrdiag;
 }
