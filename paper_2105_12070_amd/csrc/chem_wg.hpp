@@ -731,7 +731,7 @@ __device__ inline double wg_solve(const WgWs& w, const double* Mx, int NP, doubl
 #pragma unroll
       for (int c = 0; c < WNB - 1; ++c) {
         const double yc = readlane(y, l0 + c);
-        y = (inb && t > p0 + c) ? fma(-seg[c], yc, y) : y;
+        y = fma((inb && t > p0 + c) ? -seg[c] : -0.0, yc, y);  // mask off the chain
       }
       if (inb) w.vec[t] = y;
     }
@@ -762,7 +762,7 @@ __device__ inline double wg_solve(const WgWs& w, const double* Mx, int NP, doubl
 #pragma unroll
       for (int c = WNB - 1; c >= 0; --c) {
         const double xc = readlane(y * rd, l0 + c);
-        y = (inb && t < p0 + c) ? fma(-seg[c], xc, y) : y;
+        y = fma((inb && t < p0 + c) ? -seg[c] : -0.0, xc, y);
       }
       if (inb) {
         y *= rd;
