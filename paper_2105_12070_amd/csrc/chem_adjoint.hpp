@@ -86,6 +86,8 @@ template <>
 __device__ __forceinline__ Dd one<Dd>() { return Dd{1.0, 0.0}; }
 
 // Adjoint workspace in LDS (arrays of S; the double pass uses the same bytes).
+// The adjoint of sum nu g/RT of reaction r is aP[r] R_r, recomputed where it
+// is needed, so it takes no array.
 template <class S>
 struct AdjView {
   S* C;   // [66] concentrations (padding species 1)
@@ -94,11 +96,11 @@ struct AdjView {
   S* ob;  // [66] adjoint of omega (padding 0)
   S* aR;  // [R] q in the forward part, then adjoint of R_f
   S* aP;  // [R] adjoint of R_r
-  S* sn;  // [R] adjoint of sum nu g/RT
-  S* Mb;  // [R] adjoint of [M] (third-body / Troe)
+  S* Mb;  // [R - R0] adjoint of [M] of the third-body and Troe reactions
 };
 
-__host__ __device__ inline int adj_ws_doubles(int R) { return 2 * (4 * 66 + 4 * R) + 3 * R; }
+// Doubles of the workspace: room for the dual-number (two-double) pass.
+__host__ __device__ inline int adj_ws_doubles(int R, int R0) { return 2 * (4 * 66 + 2 * R + (R - R0)); }
 
 template <class S>
 __device__ inline AdjView<S> make_adj(double* base, int R) {
@@ -110,8 +112,7 @@ __device__ inline AdjView<S> make_adj(double* base, int R) {
   v.ob = b + 198;
   v.aR = b + 264;
   v.aP = v.aR + R;
-  v.sn = v.aP + R;
-  v.Mb = v.sn + R;
+  v.Mb = v.aP + R;
   return v;
 }
 
@@ -271,8 +272,7 @@ __device__ S vjp_f(const MechView& m, const AdjMech& am, const AdjView<S>& v, do
     if (r >= m.d.R0) Tbr -= Mb * Ctot * iT;
     v.aR[r] = netb;
     v.aP[r] = -netb * o.iKc;
-    v.sn[r] = sngb;
-    v.Mb[r] = Mb;
+    if (r >= m.d.R0) v.Mb[r - m.d.R0] = Mb;
     pg[3 * r + 0] += part(lnkb);
     pg[3 * r + 1] += part(lnkb * lnT);
     pg[3 * r + 2] -= part(lnkb * iT);
@@ -284,19 +284,21 @@ __device__ S vjp_f(const MechView& m, const AdjMech& am, const AdjView<S>& v, do
       const uint32_t ev = am.sent[e];
       const int r = (int)(ev >> 3), slot = (int)(ev & 7);
       const Slots s = unpack(m.sp[r]);
+      const S aP = v.aP[r];
+      const S sn = aP * (v.C[s.p0] * v.C[s.p1] * v.C[s.p2]);  // adjoint of sum nu g/RT
       if (slot < 3) {
         const int o1 = slot == 0 ? s.r1 : s.r0, o2 = slot == 2 ? s.r1 : s.r2;
         Cb += v.aR[r] * (v.C[o1] * v.C[o2]);
-        gb -= v.sn[r];
+        gb -= sn;
       } else {
         const int o1 = slot == 3 ? s.p1 : s.p0, o2 = slot == 5 ? s.p1 : s.p2;
-        Cb += v.aP[r] * (v.C[o1] * v.C[o2]);
-        gb += v.sn[r];
+        Cb += aP * (v.C[o1] * v.C[o2]);
+        gb += sn;
       }
     }
     for (int e = am.tptr[k]; e < am.tptr[k + 1]; ++e) {
       const uint32_t ev = am.tent[e];
-      Cb += v.Mb[ev >> 12] * m.tbd[ev & 0xFFF];
+      Cb += v.Mb[(ev >> 12) - m.d.R0] * m.tbd[ev & 0xFFF];
     }
   }
   hRTb += gb;
