@@ -110,9 +110,24 @@ def cpu_baseline(w, mech, st0, target_s=12.0):
     t0 = time.perf_counter()
     oracle.integrate(mech, st0[:, :n2], None, w.p_pa, w.dt, w.rtol, w.atol, nthreads=nthreads)
     t2 = time.perf_counter() - t0
+    # one core, on a smaller sample
+    n1 = max(4, min(n2, int(n2 / max(nthreads, 1) / 2)))
+    t0 = time.perf_counter()
+    oracle.integrate(mech, st0[:, :n1], None, w.p_pa, w.dt, w.rtol, w.atol, nthreads=1)
+    t3 = time.perf_counter() - t0
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n2 / t2, "unit": "cells/s", "cores": nthreads, "kind": "oracle",
             "sample": f"first {n2} of the {st0.shape[1]} cells of {w.name}, same rtol/atol, "
-                      f"OpenMP over cells, {t2:.1f} s"}
+                      f"OpenMP over cells, {t2:.1f} s",
+            "one_core": {"value": n1 / t3, "sample": f"first {n1} cells, {t3:.1f} s"},
+            "host": {"cpus": os.cpu_count(), "model": model}}
 
 
 def main():
@@ -208,7 +223,8 @@ def main():
         one_step(evs[i])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    kern_list = [a.elapsed_time(b) for a, b in evs]
+    kern_ms = float(np.mean(kern_list))
     st = status.cpu().numpy()
     sp = steps.cpu().numpy().astype(np.int64)
     rj = rejects.cpu().numpy().astype(np.int64)
@@ -236,6 +252,21 @@ def main():
         torch.cuda.synchronize()
         plain = nc / (a.elapsed_time(b) * 1e-3)
 
+    # a warm call: the same cells again from the step sizes the last call
+    # returned (the flow solver calls the chemistry again within a time step)
+    h_warm = h.clone()
+    state.copy_(st0)
+    h.copy_(h_warm)
+    wa, wb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wa.record()
+    chem.integrate(m, state, h, w.p_pa, w.dt, w.rtol, w.atol, options=opt, steps=steps, rejects=rejects,
+                   status=status)
+    wb.record()
+    torch.cuda.synchronize()
+    warm = {"cells_per_s": nc / (wa.elapsed_time(wb) * 1e-3),
+            "steps_mean": float(steps.float().mean()), "rejects_mean": float(rejects.float().mean())}
+
     value = nc * args.steps / elapsed
     out = {
         "metric": METRIC,
@@ -259,10 +290,12 @@ def main():
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(w.name, nc),
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes": nc * (16 * (w.N + 1) + 12),
-                     "kernel_ms": kern_ms, "flops_per_launch": flops},
+                     "kernel_ms": kern_ms, "kernel_ms_median": float(np.median(kern_list)),
+                     "flops_per_launch": flops},
         "steps_mean": float(sp.mean()), "rejects_mean": float(rj.mean()),
         "steps_percentiles_0_50_90_99_100": np.percentile(sp, [0, 50, 90, 99, 100]).tolist(),
         "plain_one_cell_per_block_cells_per_s": plain,
+        "warm_call": warm,
     }
     if work:
         out["seulex_work"] = work
