@@ -174,12 +174,12 @@ __global__ __launch_bounds__(WG, 2) void k_integrate_wg(IntArgs a, WgTerms tl, d
   }
 }
 
+// (mechanism tables read from global memory, as in the integrator)
 __global__ __launch_bounds__(WG) void k_rhs_jac_wg(IntArgs a, WgTerms tl, double* scratch, int NP, const double* st,
                                                    double* f, double* J) {
   extern __shared__ __align__(16) uint8_t lds[];
-  stage_blob(lds, a.blob, a.d.lds_bytes);
-  const MechView m = make_view(lds, a);
-  const WgWs w = make_wg_ws((double*)(lds + a.d.lds_bytes), a.d.R, NP);
+  const MechView m = make_view(a.blob, a);
+  const WgWs w = make_wg_ws((double*)lds, a.d.R, NP);
   double* Sx = scratch + (size_t)blockIdx.x * NP * NP;
   for (int i = threadIdx.x; i < NP * NP; i += WG) Sx[i] = 0.0;
   __syncthreads();
@@ -464,10 +464,9 @@ int set_lds_limit(const void* fn, size_t bytes) {
   return 0;
 }
 
-// LDS of the workgroup integrator (workspace only) and of the parity kernel
-// (staged tables + workspace)
+// LDS of the workgroup-path kernels (workspace only: they read the
+// mechanism tables from global memory)
 size_t wg_lds_bytes(const chem_mech* m) { return (size_t)wg_ws_doubles(m->d.R, m->wg_np) * sizeof(double); }
-size_t wg_lds_bytes_staged(const chem_mech* m) { return m->d.lds_bytes + wg_lds_bytes(m); }
 
 WgTerms wg_terms(const chem_mech* m) {
   WgTerms t;
@@ -515,7 +514,7 @@ int launch_rhs_jac_wg(chem_mech* m, const IntArgs& a, const double* st, double* 
   const int grid = wg_grid(m, a.ncells);
   const int rc = ensure_wg_scratch(m, grid, 2);
   if (rc) return rc;
-  const size_t lds = wg_lds_bytes_staged(m);
+  const size_t lds = wg_lds_bytes(m);
   HIPCHK(hipFuncSetAttribute((const void*)k_rhs_jac_wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(k_rhs_jac_wg, dim3(grid), dim3(WG), lds, s, a, wg_terms(m), m->wg_scr, m->wg_np, st, f, J);
   HIPCHK(hipGetLastError());
@@ -837,8 +836,8 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   hipDeviceGetAttribute(&m->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
   if (!wg && m->max_lds < d.lds_bytes + (int)cell_bytes(d))
     return cleanup(CHEM_EUNSUPPORTED, "mechanism workspace needs more LDS than one workgroup has");
-  if (wg && (size_t)m->max_lds < wg_lds_bytes_staged(m))
-    return cleanup(CHEM_EUNSUPPORTED, "mechanism tables and the workgroup workspace need more LDS than a workgroup has");
+  if (wg && (size_t)m->max_lds < wg_lds_bytes(m))
+    return cleanup(CHEM_EUNSUPPORTED, "the workgroup workspace needs more LDS than a workgroup has");
   if (wg) {
     if (hipMalloc(&m->wg_gptr, 4 * wgptr.size()) != hipSuccess || hipMalloc(&m->wg_grp, 4 * wgrp.size()) != hipSuccess ||
         hipMalloc(&m->wg_term, 8 * wterm.size()) != hipSuccess)

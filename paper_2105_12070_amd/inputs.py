@@ -29,6 +29,7 @@ low            [R,3] f64       lnA0, b0, theta0 of the low-pressure limit
 from __future__ import annotations
 
 import hashlib
+import math
 import os
 from dataclasses import dataclass, field
 
@@ -45,15 +46,20 @@ def _rng(seed: int) -> np.random.Generator:
     return np.random.Generator(np.random.PCG64(seed))
 
 
-def _draw_species(rng, n_species):
-    """Distinct element-count vectors with 1..MAX_ATOMS atoms.
+def _draw_species(rng, n_species, max_atoms=None):
+    """Distinct element-count vectors with 1..max_atoms atoms (MAX_ATOMS by default).
 
     The single atoms come first; later species are preferentially sums of two
     existing species so that recombination and exchange reactions exist.
     """
+    max_atoms = MAX_ATOMS if max_atoms is None else int(max_atoms)
     # small mechanisms use fewer elements (like H2/O2 chemistry), which gives
     # them enough element-balanced exchange reactions
     n_el = 2 if n_species <= 12 else (3 if n_species <= 30 else N_ELEMENTS)
+    # distinct vectors with 1..max_atoms atoms over n_el elements
+    n_distinct = math.comb(max_atoms + n_el, n_el) - 1
+    if n_species > n_distinct:
+        raise ValueError(f"{n_species} species need more than {max_atoms} atoms per species")
     comps = [tuple(int(i == e) for i in range(N_ELEMENTS)) for e in range(n_el)]
     seen = set(comps)
     while len(comps) < n_species:
@@ -61,10 +67,10 @@ def _draw_species(rng, n_species):
             i, j = rng.integers(0, len(comps), size=2)
             c = tuple(a + b for a, b in zip(comps[i], comps[j]))
         else:
-            n_at = int(rng.integers(2, MAX_ATOMS + 1))
+            n_at = int(rng.integers(2, max_atoms + 1))
             c = tuple(np.bincount(rng.integers(0, n_el, size=n_at),
                                   minlength=N_ELEMENTS).tolist())
-        if sum(c) > MAX_ATOMS or c in seen:
+        if sum(c) > max_atoms or c in seen:
             continue
         seen.add(c)
         comps.append(c)
@@ -98,7 +104,7 @@ def _pair_sums(comps):
 
 
 def make_mechanism(n_species: int, n_reactions: int, n_thirdbody: int, n_troe: int,
-                   seed: int, hf_scale: float = 1.0) -> dict:
+                   seed: int, hf_scale: float = 1.0, max_atoms: int | None = None) -> dict:
     """Draw an element-balanced, reversible mechanism.
 
     Elementary reactions are A+B<=>C+D with equal element totals on both sides;
@@ -108,7 +114,7 @@ def make_mechanism(n_species: int, n_reactions: int, n_thirdbody: int, n_troe: i
     log10 A ~ U(8,14), b ~ U(-1,2), theta ~ U(0,25000) K.
     """
     rng = _rng(seed)
-    comps = _draw_species(rng, n_species)
+    comps = _draw_species(rng, n_species, max_atoms)
     K = n_species
     n_atoms = comps.sum(axis=1)
     W = comps @ ATOMIC_WEIGHTS

@@ -36,3 +36,15 @@ def test_ambient_state_hash_and_zonal_workload():
     f = int(np.nonzero(rm["weight"])[0][0])
     # the indicator species is absent from the ambient zone and present in every reacting cell
     assert amb[1 + f] <= rm["z_max"] < st[1 + f, ~is_amb].min()
+
+
+def test_generator_species_limit():
+    """Species are distinct element-count vectors: more than the generator's
+    atom limit allows is an error, not an endless draw; a higher limit gives
+    the largest supported size."""
+    import pytest
+    from paper_2105_12070_amd.inputs import make_mechanism
+    with pytest.raises(ValueError):
+        make_mechanism(254, 1600, 160, 80, 7254)
+    m = make_mechanism(254, 1600, 160, 80, 7254, max_atoms=8)
+    assert m["n_species"] == 254 and len(set(map(tuple, m["elem"]))) == 254
