@@ -93,7 +93,7 @@ typedef struct chem_refmap {
 /* Integrator options; pass NULL for the defaults in brackets. */
 typedef struct chem_options {
   int32_t method;     /* 0 ROS4 [0], 1 Rodas3, 2 Seulex-family extrapolated linearly implicit
-                         Euler (the paper's integrator; N <= 64; step-number sequence 1..6,
+                         Euler (the paper's integrator; step-number sequence 1..6,
                          order chosen by work per unit step; J frozen per step) */
   int32_t max_steps;  /* step attempts per cell [100000] */
   double fac_safe;    /* step-size safety factor [0.9] */

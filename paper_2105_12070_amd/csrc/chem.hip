@@ -175,6 +175,31 @@ __global__ __launch_bounds__(WG, 2) void k_integrate_wg(IntArgs a, WgTerms tl, d
 }
 
 // (mechanism tables read from global memory, as in the integrator)
+// The same launch structure with the Seulex-family integrator.
+template <bool PROF>
+__global__ __launch_bounds__(WG, 2) void k_integrate_wg_sx(IntArgs a, WgTerms tl, double* scratch, int NP) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const MechView m = make_view(a.blob, a);
+  const WgWs w = make_wg_ws((double*)lds, a.d.R, NP);
+  double* Sx = scratch + (size_t)blockIdx.x * 2 * NP * NP;
+  double* Mx = Sx + (size_t)NP * NP;
+  for (int i = threadIdx.x; i < NP * NP; i += WG) Sx[i] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) w.flag[3] = atomicAdd(a.queue, 1);
+  __syncthreads();
+  int64_t idx = w.flag[3];
+  __syncthreads();
+  const int64_t lim = a.nactive ? (int64_t)*a.nactive : a.ncells;
+  while (idx < lim) {
+    const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
+    wg_integrate_cell_sx<PROF>(m, w, tl, Sx, Mx, NP, a, c);
+    if (threadIdx.x == 0) w.flag[3] = atomicAdd(a.queue, 1);
+    __syncthreads();
+    idx = w.flag[3];
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(WG) void k_rhs_jac_wg(IntArgs a, WgTerms tl, double* scratch, int NP, const double* st,
                                                    double* f, double* J) {
   extern __shared__ __align__(16) uint8_t lds[];
@@ -501,7 +526,8 @@ int launch_integrate_wg(chem_mech* m, const IntArgs& a0, hipStream_t s) {
   if ((size_t)grid * 2 * m->wg_np * m->wg_np * sizeof(double) > m->wg_scr_bytes)
     return fail(CHEM_EINVAL, "workgroup scratch not prepared");
   const size_t lds = wg_lds_bytes(m);
-  auto kern = a.prof ? k_integrate_wg<true> : k_integrate_wg<false>;
+  auto kern = a.method == 2 ? (a.prof ? k_integrate_wg_sx<true> : k_integrate_wg_sx<false>)
+                            : (a.prof ? k_integrate_wg<true> : k_integrate_wg<false>);
   HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   a.queue = m->queue;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, m->queue);
@@ -916,8 +942,8 @@ static int fill_common(const chem_mech* m, const chem_options* opt, IntArgs& a) 
   o.h_min = 1e-20;
   if (opt) o = *opt;
   if (o.method < 0 || o.method > 2) return fail(CHEM_EINVAL, "method must be 0 (ROS4), 1 (Rodas3) or 2 (Seulex)");
-  if (o.method == 2 && (m->wg || o.jac_mode || o.lu_pivot))
-    return fail(CHEM_EUNSUPPORTED, "the Seulex integrator runs on N <= 64 with the analytic Jacobian and pivoted LU");
+  if (o.method == 2 && (o.jac_mode || o.lu_pivot))
+    return fail(CHEM_EUNSUPPORTED, "the Seulex integrator uses the analytic Jacobian and pivoted LU");
   if (o.max_steps < 1 || !(o.fac_min > 0.0) || !(o.fac_max >= 1.0) || !(o.fac_safe > 0.0) || !(o.h_min >= 0.0))
     return fail(CHEM_EINVAL, "invalid controller options");
   a.method = o.method;

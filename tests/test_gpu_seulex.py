@@ -103,3 +103,53 @@ def test_seulex_instrumented_counts(chem):
     # columns 1..k take 1..k substeps: k(k+1)/2 substeps for k factorisations
     assert np.all(nsub >= 1.5 * nlu) and np.all(nsub <= 3.5 * nlu)
     print(f"[seulex counts] LU per attempt {nlu.sum() / att.sum():.2f}, substeps per LU {nsub.sum() / nlu.sum():.2f}")
+
+
+@pytest.mark.parametrize("case", ["c5_150sp", "N65"])
+def test_seulex_workgroup_path_tight(chem, case):
+    """Seulex on the workgroup path (N > 64): 150 species over 1e-10 s and the
+    first workgroup size (N = 65) over 1e-9 s, rtol 1e-10, against the oracle."""
+    from paper_2105_12070_amd.inputs import make_mechanism, make_states
+    if case == "c5_150sp":
+        w = WORKLOADS[case]
+        mech = w.mechanism()
+        st0 = w.states(mech, 4)
+        p, dt = w.p_pa, 1e-10
+    else:
+        mech = make_mechanism(64, 300, 30, 15, 7064)
+        st0 = make_states(mech, 4, 8064, [(900.0, 2200.0)])
+        p, dt = 1e6, 1e-9
+    rtol, atol = 1e-10, 1e-14
+    got, h, steps, rej, status = run(chem, mech, st0, p, dt, rtol, atol)
+    assert np.all(status == 0)
+    ref, href, rs, rr, rst = oracle.integrate(mech, st0, None, p, dt, rtol, atol, method="seulex")
+    assert np.all(rst == 0)
+    dev_ = np.abs(got - ref)
+    rel = dev_ / (np.abs(ref) + 100 * atol)
+    print(f"[seulex wg {case}] steps gpu {steps} oracle {rs}; max rel dev {rel.max():.3e}")
+    assert np.all(dev_ <= 1e-8 * np.abs(ref) + 100 * atol)
+
+
+def test_seulex_workgroup_path_metric_and_counts(chem):
+    """150 species at the metric setting: repeated launches bitwise equal, the
+    instrumented kernel takes the same steps and counts its work, sampled
+    parity with the oracle."""
+    w = WORKLOADS["c5_150sp"]
+    mech = w.mechanism()
+    st0 = w.states(mech, 40)
+    a = run(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol)
+    assert np.all(a[4] == 0)
+    pc = torch.zeros((40, 8), dtype=torch.int64, device=DEV)
+    b = run(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, phase_cycles=pc)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    pcn = pc.cpu().numpy()
+    att = a[2] + a[3]
+    assert np.all(pcn[:, 6] >= 2 * att) and np.all(pcn[:, 6] <= 6 * att)
+    idx = np.arange(0, 40, 8)
+    ref, href, rs, rr, rst = oracle.integrate(mech, st0[:, idx], None, w.p_pa, w.dt, w.rtol, w.atol,
+                                              method="seulex")
+    bound = 100 * (w.rtol * np.abs(ref) + w.atol)
+    print(f"[seulex wg metric] max dev / bound {np.max(np.abs(a[0][:, idx] - ref) / bound):.3e}; "
+          f"mean steps {a[2].mean():.1f}")
+    assert np.all(np.abs(a[0][:, idx] - ref) <= bound)
