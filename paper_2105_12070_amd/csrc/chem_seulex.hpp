@@ -1,5 +1,6 @@
-// Seulex-family integrator on the wavefront path (N <= 64): extrapolated
-// linearly implicit Euler, the paper's integrator (section 2.3).
+// Seulex-family integrator, extrapolated linearly implicit Euler, the paper's
+// integrator (section 2.3), on both layouts (wavefront path for N <= 64,
+// workgroup path above).
 //
 // Over a step H with J = J(y0) frozen, column j (1-based) takes n_j = j
 // linearly implicit Euler substeps of size h = H / n_j,
@@ -9,8 +10,8 @@
 // gains one order per column.  Column k's error is ||T_{k,k} - T_{k,k-1}||;
 // the next column among k-1, k, k+1 minimises the work per unit step
 // A_j / H_j with A_j = sum_{i<=j} (n_i + 1).  Every factorisation and solve
-// reuses the wavefront LU of the Rosenbrock path; each lane keeps its
-// component of the last two rows of the table in registers.
+// reuses the LU of the Rosenbrock path of the same layout; each lane (thread)
+// keeps its component of the last two rows of the table in registers.
 #pragma once
 #include "chem_cell.hpp"
 #include "chem_wg.hpp"
