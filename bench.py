@@ -78,10 +78,13 @@ def adjoint_flop_model(mech: dict, method_stages: int = 4, new_f: int = 3) -> di
 KERNEL_SOURCES = ("chem_common.hpp", "chem_cell.hpp", "chem.hip")
 
 
-def measured_traffic(workload: str, ncells: int):
-    """HBM bytes per launch from the committed counter summary, or None when
-    the kernel sources changed since the counters were taken (or no summary
-    covers this workload)."""
+def measured_traffic(workload: str, ncells: int, method: str = "ros4"):
+    """HBM bytes per launch of the ROS4 kernel from the committed counter
+    summary, or None when the kernel sources changed since the counters were
+    taken, no summary covers this workload, or another integrator (another
+    kernel) is timed."""
+    if method != "ros4":
+        return None
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"k_integrate_{workload}_hbm.md")
@@ -287,7 +290,7 @@ def main():
                    "n_cells": nc, "N": w.N, "variant": variant, "graph": bool(args.graph),
                    "cost_order": bool(args.cost_order)},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(w.name, nc),
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(w.name, nc, args.method),
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes": nc * (16 * (w.N + 1) + 12),
                      "kernel_ms": kern_ms, "kernel_ms_median": float(np.median(kern_list)),
