@@ -75,7 +75,7 @@ def adjoint_flop_model(mech: dict, method_stages: int = 4, new_f: int = 3) -> di
     return dict(f_replay=2 * (fm["f_step"] + fm["f_att"]), f_rev=f_rev, **fm)
 
 
-KERNEL_SOURCES = ("chem_common.hpp", "chem_cell.hpp", "chem.hip")
+KERNEL_SOURCES = ("chem_common.hpp", "chem_cell.hpp", "chem_wg.hpp", "chem.hip")
 
 
 def measured_traffic(workload: str, ncells: int, method: str = "ros4"):
