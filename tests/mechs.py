@@ -16,18 +16,19 @@ def base(K, R, comps, W, nasa):
                 low=np.zeros((R, 3)))
 
 
-def isomer_mech(kind="elementary", A=1e6, b=0.5, theta=3000.0):
-    """Species A, B (isomers with identical thermo) and an inert I; one reaction.
+def isomer_mech(kind="elementary", A=1e6, b=0.5, theta=3000.0, n_inert=1):
+    """Species A, B (isomers with identical thermo) and n_inert copies of an
+    inert I; one reaction.
 
     kind: "elementary" (A <=> B), "thirdbody" (A + M <=> B + M, unit
     efficiencies) or "troe" (A (+M) <=> B (+M)).  K_c = 1 and the reaction is
     thermoneutral, so T stays constant and Y_A - Y_B decays as exp(-2 k t).
     """
-    comps = [[1, 2, 0, 0], [1, 2, 0, 0], [0, 0, 0, 2]]
-    W = [14.027, 14.027, 28.014]
-    nasa = [nasa_row(4.0, -1000.0, 5.0, a2=1e-3), nasa_row(4.0, -1000.0, 5.0, a2=1e-3),
-            nasa_row(3.5, -500.0, 4.0)]
-    m = base(3, 1, comps, W, nasa)
+    comps = [[1, 2, 0, 0], [1, 2, 0, 0]] + [[0, 0, 0, 2]] * n_inert
+    W = [14.027, 14.027] + [28.014] * n_inert
+    nasa = [nasa_row(4.0, -1000.0, 5.0, a2=1e-3), nasa_row(4.0, -1000.0, 5.0, a2=1e-3)] + \
+        [nasa_row(3.5, -500.0, 4.0)] * n_inert
+    m = base(2 + n_inert, 1, comps, W, nasa)
     m["reac"][0, 0] = 0
     m["prod"][0, 0] = 1
     m["lnA"][0], m["b"][0], m["theta"][0] = np.log(A), b, theta

@@ -95,6 +95,7 @@ def dot_product_check(chem, name, nc, dt, rtol, atol, ndir, tol, seed=7, max_tap
             scale += np.abs(lam[:, c]) @ np.abs(dyo)
         rhs_s = np.sum(lam0 * dy0) + sum(grad[i] @ dp[i] for i in range(3))
         err = abs(rhs_s - lhs) / scale
+        assert np.isfinite(err), (lhs, rhs_s)  # max() below would drop a NaN
         worst = max(worst, err)
         say(f"  dir {d}: oracle {lhs:.12e}  gpu {rhs_s:.12e}  rel {err:.2e}")
     assert worst <= tol, worst
