@@ -125,7 +125,6 @@ __global__ __launch_bounds__(max_threads<NP>()) void k_rhs_jac(IntArgs a, const 
 
 template <int NP>
 __global__ __launch_bounds__(256) void k_lu_solve(int64_t nmat, int n, const double* A, double* b, int32_t* info) {
-  __shared__ double bcast[4][64];
   __shared__ int slots[4][64];
   const int wv = threadIdx.x / WAVE;
   const int64_t mi = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
@@ -136,7 +135,7 @@ __global__ __launch_bounds__(256) void k_lu_solve(int64_t nmat, int n, const dou
   for (int j = 0; j < NP; ++j) row[j] = (lane < n && j < n) ? A[((size_t)mi * n + lane) * n + j] : 0.0;
   int mystep;
   double myrdiag;
-  const int rc = lu_factor<NP>(row, n, lane, mystep, myrdiag, bcast[wv]);
+  const int rc = lu_factor<NP>(row, n, lane, mystep, myrdiag);
   if (lane == 0) info[mi] = rc;
   if (rc) return;
   const int src = permute_rows<NP>(row, n, lane, mystep, myrdiag, slots[wv]);

@@ -9,10 +9,6 @@
 #pragma once
 #include "chem_common.hpp"
 
-#ifndef CHEM_LU_BCAST_LDS
-#define CHEM_LU_BCAST_LDS 0
-#endif
-
 namespace chem {
 
 struct MechView {
@@ -61,13 +57,12 @@ struct CellWs {
   double* C;    // [64+1] concentrations, C[K] = 1 (padding species)
   double* g;    // [64+1] g/RT (reused for mass enthalpy in the Jacobian pass)
   double* hR;   // [64+1] h/RT
-  double* bc;   // [64] pivot-row broadcast buffer of the LU
   int* slot;    // [64] row permutation scratch
 };
 
 // S = NP + 1, so reads of static columns j < NP + 1 from any row stay inside
 // the J block (its last row is followed by the reaction arrays).
-__host__ __device__ inline int cell_ws_doubles(int N, int S, int R) { return N * S + 4 * R + 3 * 66 + 64 + 32; }
+__host__ __device__ inline int cell_ws_doubles(int N, int S, int R) { return N * S + 4 * R + 3 * 66 + 32; }
 
 __device__ inline CellWs make_ws(double* base, const MechDims& d) {
   CellWs w;
@@ -79,8 +74,7 @@ __device__ inline CellWs make_ws(double* base, const MechDims& d) {
   w.C = w.rdt + d.R;
   w.g = w.C + 66;
   w.hR = w.g + 66;
-  w.bc = w.hR + 66;
-  w.slot = (int*)(w.bc + 64);
+  w.slot = (int*)(w.hR + 66);
   return w;
 }
 
@@ -489,8 +483,8 @@ __device__ __forceinline__ double recip(double x) {
 // Inside a phase the four columns of chunk P rotate through c0..c3 so that
 // the pivot column is always c0; every register index is static.
 // Returns the 1-based step of a zero pivot, or 0.
-template <int NP, bool BCAST_LDS = CHEM_LU_BCAST_LDS>
-__device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep, double& myrdiag, double* bc,
+template <int NP>
+__device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep, double& myrdiag,
                                 bool nopiv = false) {
   mystep = lane < N ? -1 : (1 << 20);
   myrdiag = 0.0;
@@ -522,25 +516,7 @@ __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep,
       }
       const double l = upd ? c0 * rp : 0.0;
       // c1..c3 hold columns k+1.. of the chunk first, then finished columns
-      double u1, u2, u3;
-      if (BCAST_LDS) {
-        // the pivot lane publishes its row in LDS, every lane reads it back
-        if (lane == p) {
-          bc[1] = c1;
-          bc[2] = c2;
-          bc[3] = c3;
-#pragma unroll
-          for (int j = k0 + 4; j < NP; ++j) bc[j - k0] = row[j];
-        }
-        wsync();
-        u1 = bc[1];
-        u2 = bc[2];
-        u3 = bc[3];
-      } else {
-        u1 = readlane(c1, p);
-        u2 = readlane(c2, p);
-        u3 = readlane(c3, p);
-      }
+      double u1 = readlane(c1, p), u2 = readlane(c2, p), u3 = readlane(c3, p);
       u1 = kk <= 2 ? u1 : 0.0;
       u2 = kk <= 1 ? u2 : 0.0;
       u3 = kk == 0 ? u3 : 0.0;
@@ -548,24 +524,18 @@ __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep,
       c2 = fma(-l, u2, c2);
       c3 = fma(-l, u3, c3);
       c0 = upd ? l : c0;
-      if (BCAST_LDS) {
+      // four broadcasts in flight before their four FMAs: the scalar
+      // registers differ, so no broadcast waits on the previous FMA
 #pragma unroll
-        for (int j = k0 + 4; j < NP; ++j) row[j] = fma(-l, bc[j - k0], row[j]);
-      } else {
-        // four broadcasts in flight before their four FMAs: the scalar
-        // registers differ, so no broadcast waits on the previous FMA
-#pragma unroll
-        for (int j = k0 + 4; j < NP; j += 4) {
-          const double u0 = readlane(row[j], p), v1 = readlane(row[j + 1], p);
-          const double v2 = readlane(row[j + 2], p), v3 = readlane(row[j + 3], p);
-          __builtin_amdgcn_sched_barrier(0);
-          row[j] = fma(-l, u0, row[j]);
-          row[j + 1] = fma(-l, v1, row[j + 1]);
-          row[j + 2] = fma(-l, v2, row[j + 2]);
-          row[j + 3] = fma(-l, v3, row[j + 3]);
-        }
+      for (int j = k0 + 4; j < NP; j += 4) {
+        const double u0 = readlane(row[j], p), v1 = readlane(row[j + 1], p);
+        const double v2 = readlane(row[j + 2], p), v3 = readlane(row[j + 3], p);
+        __builtin_amdgcn_sched_barrier(0);
+        row[j] = fma(-l, u0, row[j]);
+        row[j + 1] = fma(-l, v1, row[j + 1]);
+        row[j + 2] = fma(-l, v2, row[j + 2]);
+        row[j + 3] = fma(-l, v3, row[j + 3]);
       }
-      if (BCAST_LDS) wsync();
       const double t = c0;
       c0 = c1;
       c1 = c2;
@@ -669,7 +639,7 @@ __device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosT
   const bool okm = form_matrix<NP>(w, N, m.d.S, lane, 1.0 / (tab.gamma * h), row);
   pf.stop(1);
   if (!okm) return 2;
-  const int info = lu_factor<NP>(row, N, lane, mystep, myrdiag, w.bc, PROF && nopiv);
+  const int info = lu_factor<NP>(row, N, lane, mystep, myrdiag, PROF && nopiv);
   if (info) {
     pf.stop(2);
     return 1;

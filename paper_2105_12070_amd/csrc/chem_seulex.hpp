@@ -81,7 +81,7 @@ __device__ void integrate_cell_sx(const MechView& m, const CellWs& w, const IntA
         const bool okm = form_matrix<NP>(w, N, m.d.S, lane, 1.0 / h, row);
         pf.stop(1);
         if (!okm) { rc = 2; break; }
-        const int info = lu_factor<NP>(row, N, lane, mystep, myrdiag, w.bc);
+        const int info = lu_factor<NP>(row, N, lane, mystep, myrdiag);
         if (info) {
           pf.stop(2);
           rc = 1;
