@@ -435,10 +435,15 @@ __device__ inline void wg_panel(const WgWs& w, int p0, int NP, int lane) {
     const unsigned long long key = __builtin_bit_cast(unsigned long long, best < 0.0 ? 0.0 : best);
     const unsigned hi = (unsigned)(key >> 32), lo = (unsigned)key;
     const unsigned mh = wave_max_u32(best < 0.0 ? 0u : hi);
-    const unsigned ml = wave_max_u32((best >= 0.0 && hi == mh) ? lo : 0u);
+    // the low halves decide only between lanes that tie on the high half
+    const bool top = best >= 0.0 && hi == mh;
+    bool holder = top;
+    if (__builtin_popcountll(ballot(top)) > 1) {
+      const unsigned ml = wave_max_u32(top ? lo : 0u);
+      holder = top && lo == ml;
+    }
     // first row holding the maximum: the lowest slot with a holder, then the
     // lowest lane in it (one ballot per slot)
-    const bool holder = best >= 0.0 && hi == mh && lo == ml;
     int pr = kk;
 #pragma unroll
     for (int sl = NS - 1; sl >= 0; --sl) {
@@ -447,17 +452,27 @@ __device__ inline void wg_panel(const WgWs& w, int p0, int NP, int lane) {
     }
     pr = pr < nrow ? pr : kk;
     const int lp = pr & (WAVE - 1), sp = pr / WAVE;
+    // the pivot row's slot is wave-uniform: a scalar branch picks it.  The
+    // update needs columns kk.. of the pivot row; the columns left of kk only
+    // move with a row interchange, so they are broadcast only then.
     double b[WNB];
 #pragma unroll
-    for (int c = 0; c < WNB; ++c) {
-      double x = P[0][c];
+    for (int sl = 0; sl < NS; ++sl) {
+      if (sp == sl) {
 #pragma unroll
-      for (int sl = 1; sl < NS; ++sl) x = sp == sl ? P[sl][c] : x;
-      b[c] = readlane(x, lp);
+        for (int c = kk; c < WNB; ++c) b[c] = readlane(P[sl][c], lp);
+      }
     }
     const double pv = b[kk];
     const bool sing = !(pv != 0.0);
     if (!sing && pr != kk) {
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) {
+        if (sp == sl) {
+#pragma unroll
+          for (int c = 0; c < kk; ++c) b[c] = readlane(P[sl][c], lp);
+        }
+      }
 #pragma unroll
       for (int c = 0; c < WNB; ++c) {
         const double a = readlane(P[0][c], kk);
@@ -568,7 +583,10 @@ __device__ inline int wg_lu(const WgWs& w, double* Mx, int NP, Prof<PROF>* pf = 
     __syncthreads();
     if (PROF) tp = pf->now();
     if (wv == 0) {
-      if (nrow <= 3 * WAVE) wg_panel<3>(w, p0, NP, lane);
+      // as many 64-row register slots as the panel has rows
+      if (nrow <= WAVE) wg_panel<1>(w, p0, NP, lane);
+      else if (nrow <= 2 * WAVE) wg_panel<2>(w, p0, NP, lane);
+      else if (nrow <= 3 * WAVE) wg_panel<3>(w, p0, NP, lane);
       else wg_panel_lds(w, p0, NP, lane);
       // the panel's 16 interchanges composed on the rows they touch (at most
       // 32, one per lane): afterwards row sdst[i] holds old row ssrc[i]
