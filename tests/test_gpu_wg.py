@@ -70,6 +70,27 @@ def test_lu_solve_matches_lapack_large(chem, n):
         np.testing.assert_allclose(x[i], ref, rtol=1e-7, atol=1e-9 * np.abs(ref).max())
 
 
+@pytest.mark.parametrize("n", [100, 151, 256])
+def test_lu_solve_pivot_ties_large(chem, n):
+    """Entries from {+-1, +-(1 + 2^-40), +-2}: columns hold many pivot candidates
+    of equal magnitude (exact ties) and of equal upper 32 bits that differ only
+    in the lower bits, so the pivot search takes its tie-breaking path."""
+    rng = np.random.default_rng(100 + n)
+    nmat = 6
+    vals = np.array([1.0, 1.0 + 2.0 ** -40, 2.0])
+    A = rng.choice(vals, (nmat, n, n)) * rng.choice([-1.0, 1.0], (nmat, n, n))
+    b = rng.standard_normal((nmat, n))
+    x, info = chem.lu_solve(torch.tensor(A, device=DEV), torch.tensor(b, device=DEV))
+    torch.cuda.synchronize()
+    x, info = x.cpu().numpy(), info.cpu().numpy()
+    assert np.all(info == 0)
+    for i in range(nmat):
+        ref = np.linalg.solve(A[i], b[i])
+        res = np.abs(A[i] @ x[i] - b[i]).max() / (np.abs(A[i]).max() * np.abs(x[i]).max())
+        assert res <= 20 * n * np.finfo(float).eps, (i, res)
+        np.testing.assert_allclose(x[i], ref, rtol=1e-6, atol=1e-8 * np.abs(ref).max())
+
+
 def test_lu_zero_pivot_large(chem):
     rng = np.random.default_rng(5)
     A = rng.standard_normal((2, 100, 100))
