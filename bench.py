@@ -78,25 +78,37 @@ def adjoint_flop_model(mech: dict, method_stages: int = 4, new_f: int = 3) -> di
 KERNEL_SOURCES = ("chem_common.hpp", "chem_cell.hpp", "chem_wg.hpp", "chem.hip")
 
 
+def kernel_source_hash(root: str = ROOT) -> str:
+    """sha256 over the integration kernel's sources with comments, trailing
+    blanks and empty lines removed: a change of code changes it, a change of
+    comments does not."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(root, "paper_2105_12070_amd", "csrc", f)) as fh:
+            txt = fh.read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", "", txt)
+        lines = [ln.rstrip() for ln in txt.split("\n")]
+        h.update("\n".join(ln for ln in lines if ln).encode())
+    return h.hexdigest()
+
+
 def measured_traffic(workload: str, ncells: int, method: str = "ros4"):
     """HBM bytes per launch of the ROS4 kernel from the committed counter
-    summary, or None when the kernel sources changed since the counters were
+    summary, or None when the kernel code changed since the counters were
     taken, no summary covers this workload, or another integrator (another
     kernel) is timed."""
     if method != "ros4":
         return None
-    import hashlib
     import re
     path = os.path.join(ROOT, "profiles", f"k_integrate_{workload}_hbm.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2105_12070_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
     m = {k: v for k, v in re.findall(r"^(\w+): (.+)$", txt, flags=re.M)}
-    if m.get("source_sha256") != h.hexdigest() or m.get("workload") != f"{workload} {ncells}":
+    if m.get("source_sha256") != kernel_source_hash() or m.get("workload") != f"{workload} {ncells}":
         return None
     return float(m["fetch_bytes_per_launch"]) + float(m["write_bytes_per_launch"])
 

@@ -6,10 +6,11 @@
 // matrices in a global scratch slot (L2/MALL resident while the cell is
 // worked on): Sx, the sparse part of d omega/dC at its structural positions,
 // and Mx, the matrix being factored.  The LU is blocked by 16 columns: the
-// panel is factored in LDS by one wave (partial pivoting, first largest |a|),
-// its row interchanges are applied to the other columns, the 16 rows of U are
-// formed by a triangular solve, and the trailing matrix takes one rank-16
-// update per panel (4 x 4 register blocks, operands from LDS).  The Jacobian
+// panel is staged in LDS and factored by one wave (in registers up to 192
+// rows; partial pivoting, first largest |a|), its row interchanges are
+// applied to the other columns, the 16 rows of U are formed by a triangular
+// solve, and the trailing matrix takes one rank-16 update per panel on FP64
+// MFMA (16 x 16 output tiles, operands from LDS).  The Jacobian
 // is assembled without atomics: every species row walks a host-built list of
 // its nonzero columns, each with the reaction terms that contribute to it, in
 // a fixed order.  All sums over threads are fixed-order, so results are
