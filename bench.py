@@ -63,16 +63,19 @@ def flop_model(mech: dict, method_stages: int = 4, new_f: int = 2) -> dict:
 def adjoint_flop_model(mech: dict, method_stages: int = 4, new_f: int = 3) -> dict:
     """Algorithmic FP64 operations of one reverse step (estimates, transcendentals count 1).
 
-    Each accepted step is replayed twice (segment replay and reverse replay:
-    Jacobian pass + one attempt each).  The reverse step takes s transposed
-    solves, s dual-number vector-Jacobian products of f (the second-order
-    terms, costed as 3 first-order ones) and one first-order product per new f
-    evaluation (stage sources); a first-order product of f costs ~3 f.
+    With checkpoints every few steps, each accepted step has to be recomputed
+    once from its checkpoint (Jacobian pass + one attempt); the kernel keeps
+    that replay's factors and stages for the backward pass, replaying only the
+    last step of each segment a second time, which is not counted.  The
+    reverse step takes s transposed solves, s dual-number vector-Jacobian
+    products of f (the second-order terms, costed as 3 first-order ones) and
+    one first-order product per new f evaluation (stage sources); a
+    first-order product of f costs ~3 f.
     """
     fm = flop_model(mech)
     f_vjp = 3 * fm["f_rhs"]
     f_rev = method_stages * (fm["f_solve"] + 3 * f_vjp) + new_f * f_vjp
-    return dict(f_replay=2 * (fm["f_step"] + fm["f_att"]), f_rev=f_rev, **fm)
+    return dict(f_replay=fm["f_step"] + fm["f_att"], f_rev=f_rev, **fm)
 
 
 KERNEL_SOURCES = ("chem_common.hpp", "chem_cell.hpp", "chem_wg.hpp", "chem.hip")
