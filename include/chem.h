@@ -172,6 +172,16 @@ int chem_integrate_adjoint(const chem_mech* mech, int64_t ncells, int64_t ld, co
                            int32_t checkpoint_every, int32_t max_tape, int32_t* steps, int32_t* status,
                            void* stream);
 
+/* Upper bound, in bytes, of the per-step records that chem_integrate_adjoint
+ * keeps for the backward walk of a checkpoint segment (every lane's factor
+ * row, pivot step, 1/U_kk and stage values: ncells x checkpoint_every x
+ * (NP + 6) x 64 doubles, NP = N rounded up to 16, 32, 56 or 64; device memory
+ * owned by the library).  When the records would exceed it, the backward walk
+ * replays every step from the segment's states instead: slower, the same
+ * results bit for bit.  Default 8 GiB; 0 turns the records off.  Process-wide,
+ * for later calls; returns CHEM_OK. */
+int chem_set_adjoint_record_budget(uint64_t bytes);
+
 /* Parity entry points for the individual steps of the method.
  * chem_rhs      : f(Phi) of every cell, f is device [N][ld] (Eq. 1).
  * chem_jacobian : J = df/dPhi of every cell, J is device [ncells][N][N]

@@ -92,6 +92,7 @@ def lib():
         L.chem_jacobian.argtypes = [vp, i64, i64, vp, d, vp, vp, vp]
         L.chem_lu_solve.argtypes = [i64, i32, vp, vp, vp, vp]
         L.chem_autotune.argtypes = [vp, i64, i64, vp, vp, d, d, d, d, vp, vp, vp]
+        L.chem_set_adjoint_record_budget.argtypes = [C.c_uint64]
         _lib = L
     return _lib
 
@@ -276,6 +277,12 @@ def autotune(mech: Mechanism, state, h, p, dt, rtol=1e-6, atol=1e-10):
     return dict(persistent=v[0], waves_per_block=v[1], grid_mult=v[2]), ms.value
 
 
+def set_adjoint_record_budget(nbytes: int) -> None:
+    """chem_set_adjoint_record_budget: bytes of per-step records the adjoint
+    may keep for its backward walk (0 = replay every step)."""
+    _check(lib().chem_set_adjoint_record_budget(int(nbytes)))
+
+
 EXPORTED = ["chem_load_mechanism", "chem_free_mechanism", "chem_max_n", "chem_mech_sizes", "chem_set_arrhenius",
-            "chem_integrate", "chem_integrate_adjoint", "chem_rhs", "chem_jacobian", "chem_lu_solve",
-            "chem_autotune", "chem_last_error"]
+            "chem_integrate", "chem_integrate_adjoint", "chem_set_adjoint_record_budget", "chem_rhs",
+            "chem_jacobian", "chem_lu_solve", "chem_autotune", "chem_last_error"]

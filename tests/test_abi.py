@@ -34,6 +34,12 @@ def test_exports_every_declared_symbol(L):
     assert sorted(chem.EXPORTED) == names
 
 
+def test_adjoint_record_budget_setter(L):
+    # host-side setting only; restores the default
+    assert L.chem_set_adjoint_record_budget(C.c_uint64(0)) == 0
+    assert L.chem_set_adjoint_record_budget(C.c_uint64(8 << 30)) == 0
+
+
 def test_max_n(L):
     assert L.chem_max_n() == 255  # wavefront path up to 64, workgroup path above
 

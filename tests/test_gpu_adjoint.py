@@ -248,6 +248,25 @@ def test_adjoint_checkpoint_interval_invariance(chem):
             assert np.array_equal(a, b)
 
 
+def test_adjoint_replay_path_equals_records(chem):
+    """With the per-step record budget at 0 the backward walk replays every
+    step instead of loading the records of the segment's forward replay: the
+    same arithmetic, so every output is bitwise equal."""
+    w = WORKLOADS["c4_adj"]
+    mech = w.mechanism()
+    st0 = np.ascontiguousarray(w.states(mech)[:, :96])
+    lam = objective_lambda(mech["n_species"], 96)
+    ref = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, lam, ck=8)
+    assert np.all(ref[4] == 0)
+    chem.set_adjoint_record_budget(0)
+    try:
+        got = gpu_adjoint(chem, mech, st0, w.p_pa, w.dt, w.rtol, w.atol, lam, ck=8)
+    finally:
+        chem.set_adjoint_record_budget(8 << 30)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
+
+
 def test_adjoint_forward_equals_integrate(chem):
     """The forward half of the adjoint is the plain integrator, bit for bit."""
     w = WORKLOADS["c4_adj"]
