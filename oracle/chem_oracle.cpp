@@ -307,7 +307,7 @@ void jac_analytic(const OracleMech& m, const Params<S>& P, double p, const S* y,
   Mix<S> x;
   mixture(m, p, y, x);
   std::vector<S> omega(K, S(0.0)), dwdT(K, S(0.0)), dwdC((size_t)K * K, S(0.0));
-  std::vector<S> dRf(K), dRr(K);
+  std::vector<S> dRf(K), dRr(K), dqdC(K);
   for (int r = 0; r < m.R; ++r) {
     Rate<S> rt = rate(m, P, x, r);
     const int* re = m.reac + 3 * r;
@@ -329,7 +329,6 @@ void jac_analytic(const OracleMech& m, const Params<S>& P, double p, const S* y,
       }
     }
     S net = rt.Rf - rt.Rr / rt.Kc;
-    std::vector<S> dqdC(K);
     for (int j = 0; j < K; ++j) {
       dqdC[j] = rt.keff * (dRf[j] - dRr[j] / rt.Kc);
       if (m.rtype[r] != 0) dqdC[j] += rt.dkeff_dM * m.eff[(size_t)r * K + j] * net;
@@ -666,6 +665,32 @@ double sx_err(int N, const std::vector<double>& a, const std::vector<double>& b,
   return std::sqrt(s2 / N);
 }
 
+// One record per step attempt, for the controller pins: the step size tried,
+// the scaled error norm (NaN when none was formed), the outcome and, for the
+// Seulex family, the column count k of the attempt.
+enum { AT_ACCEPT = 0, AT_REJECT_ERR = 1, AT_REJECT_NONFINITE = 2, AT_REJECT_SINGULAR = 3, AT_REJECT_UNSTABLE = 4 };
+struct Attempt {
+  double h, err;
+  int outcome, k;
+};
+
+// The chemistry system: N = K + 1, f and J at a state (J analytic or by
+// one-sided differences, the ablation's jac_mode 1).  A state is valid if it is
+// finite with T > 0.
+struct ChemSystem {
+  const OracleMech& m;
+  Params<double> P;
+  double p;
+  int jac_mode;
+  int size() const { return m.K + 1; }
+  bool valid(const double* y) const { return all_finite(y, m.K + 1) && y[0] > 0.0; }
+  void f(const double* y, double* out) const { rhs(m, P, p, y, out); }
+  void jac(const double* y, double* J, double* f0) const {
+    if (jac_mode == 1) jac_fd(m, P, p, y, J, f0);
+    else jac_analytic(m, P, p, y, J, f0);
+  }
+};
+
 // Adaptive Seulex integration of one cell over [0, dt].  Order control: the
 // target column k starts at 3; after an accepted step the next k among k-1,
 // k, k+1 minimises the work per unit step A_j / H_j, with A_j = sum_{i<=j}
@@ -674,11 +699,11 @@ double sx_err(int N, const std::vector<double>& a, const std::vector<double>& b,
 // fac_min / fac_max.  Rejections keep k and take H_k; the controller's other
 // rules (clipping to dt, no growth after a rejection, h_out, limits, halving
 // on a singular matrix) are those of the Rosenbrock path.
-CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, double rtol, double atol,
-                                 const OracleOpts& o, double* y, double* h_io, std::vector<double>* hs_out) {
-  const int N = m.K + 1;
-  Params<double> P{m.lnA, m.b, m.theta};
-  auto frhs = [&](const double* yy, double* ff) { rhs(m, P, p, yy, ff); };
+template <class Sys>
+CellResult integrate_seulex(const Sys& sys, double dt, double rtol, double atol, const OracleOpts& o, double* y,
+                            double* h_io, std::vector<double>* hs_out, std::vector<Attempt>* trace = nullptr) {
+  const int N = sys.size();
+  auto frhs = [&](const double* yy, double* ff) { sys.f(yy, ff); };
   CellResult res{ST_OK, 0, 0};
   std::vector<double> f0(N), J((size_t)N * N);
   std::vector<std::vector<std::vector<double>>> T(SX_KMAX, std::vector<std::vector<double>>(SX_KMAX,
@@ -687,7 +712,7 @@ CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, doubl
   A[0] = 0.0;
   for (int j = 1; j <= SX_KMAX + 1; ++j) A[j] = A[j - 1] + (j + 1);
   double h_prop = (std::isfinite(*h_io) && *h_io > 0.0) ? std::min(*h_io, dt) : dt;
-  if (!all_finite(y, N) || !(y[0] > 0.0)) {
+  if (!sys.valid(y)) {
     res.status = ST_NONFINITE;
     *h_io = h_prop;
     return res;
@@ -699,9 +724,11 @@ CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, doubl
   auto hopt = [&](double H, double err, int j) {
     return H * std::min(o.fac_max, std::max(o.fac_min, o.fac_safe * std::pow(err, -1.0 / j)));
   };
+  auto rec = [&](double H, double err, int outcome) {
+    if (trace) trace->push_back(Attempt{H, err, outcome, k});
+  };
   while (tcur < dt) {
-    if (o.jac_mode == 1) jac_fd(m, P, p, y, J.data(), f0.data());
-    else jac_analytic(m, P, p, y, J.data(), f0.data());
+    sys.jac(y, J.data(), f0.data());
     if (!all_finite(f0.data(), N) || !all_finite(J.data(), N * N)) { res.status = ST_NONFINITE; break; }
     int nsing = 0;
     bool accepted = false;
@@ -714,6 +741,7 @@ CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, doubl
       ++attempts;
       const int rc = seulex_table(N, frhs, y, f0.data(), J.data(), H, k, T, o.lu_pivot == 0, rtol, atol);
       if (rc == 1) {
+        rec(H, NAN, AT_REJECT_SINGULAR);
         ++res.rejects;
         if (++nsing > 5) { res.status = ST_SINGULAR; break; }
         h_prop = 0.5 * H;
@@ -721,6 +749,7 @@ CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, doubl
         continue;
       }
       if (rc == 2) {  // unstable substeps
+        rec(H, NAN, AT_REJECT_UNSTABLE);
         ++res.rejects;
         h_prop = 0.5 * H;
         rejected_last = true;
@@ -729,6 +758,7 @@ CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, doubl
       const std::vector<double>& yk = T[k - 1][k - 1];
       const double errk = sx_err(N, yk, T[k - 1][k - 2], y, rtol, atol);
       if (!std::isfinite(errk) || !all_finite(yk.data(), N)) {
+        rec(H, errk, AT_REJECT_NONFINITE);
         ++res.rejects;
         h_prop = o.fac_min * H;
         rejected_last = true;
@@ -742,6 +772,7 @@ CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, doubl
         if (std::isfinite(e1)) Hk1 = hopt(H, e1, k - 1);
       }
       if (errk <= 1.0) {
+        rec(H, errk, AT_ACCEPT);
         accepted = true;
         ++res.steps;
         if (hs_out) hs_out->push_back(H);
@@ -765,6 +796,7 @@ CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, doubl
         k = knew;
         rejected_last = false;
       } else {
+        rec(H, errk, AT_REJECT_ERR);
         ++res.rejects;
         h_prop = Hk;
         rejected_last = true;
@@ -776,18 +808,19 @@ CellResult integrate_cell_seulex(const OracleMech& m, double p, double dt, doubl
   return res;
 }
 
-// Adaptive integration of one cell over [0, dt] (controller constants in opts).
-CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol, double atol, const OracleOpts& o,
-                          double* y, double* h_io, std::vector<double>* hs_out) {
-  if (o.method == 3) return integrate_cell_seulex(m, p, dt, rtol, atol, o, y, h_io, hs_out);
-  const int N = m.K + 1;
-  const Table t = table_of(o.method);
-  Params<double> P{m.lnA, m.b, m.theta};
-  auto frhs = [&](const double* yy, double* ff) { rhs(m, P, p, yy, ff); };
+// Adaptive Rosenbrock integration of one cell over [0, dt] (controller
+// constants in opts; the rules are listed with the C API below).
+template <class Sys>
+CellResult integrate_ros(const Sys& sys, int method, double dt, double rtol, double atol, const OracleOpts& o,
+                         double* y, double* h_io, std::vector<double>* hs_out,
+                         std::vector<Attempt>* trace = nullptr) {
+  const int N = sys.size();
+  const Table t = table_of(method);
+  auto frhs = [&](const double* yy, double* ff) { sys.f(yy, ff); };
   CellResult res{ST_OK, 0, 0};
   std::vector<double> f0(N), J((size_t)N * N), yn(N), err(N);
   double h_prop = (std::isfinite(*h_io) && *h_io > 0.0) ? std::min(*h_io, dt) : dt;
-  if (!all_finite(y, N) || !(y[0] > 0.0)) {
+  if (!sys.valid(y)) {
     res.status = ST_NONFINITE;
     *h_io = h_prop;
     return res;
@@ -795,9 +828,11 @@ CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol,
   double tcur = 0.0;
   bool rejected_last = false;
   int attempts = 0;
+  auto rec = [&](double h, double e, int outcome) {
+    if (trace) trace->push_back(Attempt{h, e, outcome, 0});
+  };
   while (tcur < dt) {
-    if (o.jac_mode == 1) jac_fd(m, P, p, y, J.data(), f0.data());
-    else jac_analytic(m, P, p, y, J.data(), f0.data());
+    sys.jac(y, J.data(), f0.data());
     if (!all_finite(f0.data(), N) || !all_finite(J.data(), N * N)) { res.status = ST_NONFINITE; break; }
     int nsing = 0;
     bool accepted = false;
@@ -809,6 +844,7 @@ CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol,
       if (h >= dt - tcur) { h = dt - tcur; clipped = true; }
       ++attempts;
       if (ros_step(t, N, frhs, y, f0.data(), J.data(), h, yn.data(), err.data(), o.lu_pivot == 0)) {
+        rec(h, NAN, AT_REJECT_SINGULAR);
         ++res.rejects;
         if (++nsing > 5) { res.status = ST_SINGULAR; break; }
         h_prop = 0.5 * h;
@@ -824,6 +860,7 @@ CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol,
       }
       double enorm = std::sqrt(s2 / N);
       if (!std::isfinite(enorm) || !all_finite(yn.data(), N)) {
+        rec(h, enorm, AT_REJECT_NONFINITE);
         ++res.rejects;
         h_prop = o.fac_min * h;
         rejected_last = true;
@@ -831,6 +868,7 @@ CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol,
       }
       double fac = std::min(o.fac_max, std::max(o.fac_min, o.fac_safe * std::pow(enorm, -1.0 / t.order_err)));
       if (enorm <= 1.0) {
+        rec(h, enorm, AT_ACCEPT);
         accepted = true;
         ++res.steps;
         if (hs_out) hs_out->push_back(h);
@@ -842,6 +880,7 @@ CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol,
         h_prop = hnew;
         rejected_last = false;
       } else {
+        rec(h, enorm, AT_REJECT_ERR);
         ++res.rejects;
         h_prop = h * fac;
         rejected_last = true;
@@ -851,6 +890,34 @@ CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol,
   }
   *h_io = std::min(h_prop, dt);
   return res;
+}
+
+// Linear test system for the controller pins: y' = diag(lam) y, J = diag(lam)
+// exactly; component i of f is NaN where |y_i| > bound (bound <= 0: none).
+// Every step of a Rosenbrock or extrapolation method on it is a rational
+// function of h lam_i, so the whole controller trace has a closed form.
+struct DiagSystem {
+  int n;
+  const double* lam;
+  double bound;
+  int size() const { return n; }
+  bool valid(const double* y) const { return all_finite(y, n); }
+  void f(const double* y, double* out) const {
+    for (int i = 0; i < n; ++i) out[i] = (bound > 0.0 && std::fabs(y[i]) > bound) ? NAN : lam[i] * y[i];
+  }
+  void jac(const double* y, double* J, double* f0) const {
+    f(y, f0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) J[(size_t)i * n + j] = i == j ? lam[i] : 0.0;
+  }
+};
+
+// Adaptive integration of one chemistry cell over [0, dt].
+CellResult integrate_cell(const OracleMech& m, double p, double dt, double rtol, double atol, const OracleOpts& o,
+                          double* y, double* h_io, std::vector<double>* hs_out) {
+  const ChemSystem sys{m, Params<double>{m.lnA, m.b, m.theta}, p, o.jac_mode};
+  if (o.method == 3) return integrate_seulex(sys, dt, rtol, atol, o, y, h_io, hs_out);
+  return integrate_ros(sys, o.method, dt, rtol, atol, o, y, h_io, hs_out);
 }
 
 // Replay accepted steps hs[0..n) from y0 without the controller, in scalar type S.
@@ -1083,6 +1150,31 @@ int oracle_tlm(const OracleMech* m, double p_pa, int method, const double* y0, c
     dyout[i] = yo[i].d;
   }
   return rc;
+}
+
+// The adaptive integrators on the linear test system DiagSystem (n components,
+// rates lam, NaN bound), with every step attempt recorded: trace[a] = (h, err,
+// outcome, k) for a < min(attempts, cap); outcome 0 accepted, 1 rejected on
+// the error, 2 rejected on a non-finite error, 3 singular matrix, 4 unstable
+// substeps.  method 0 ROS4, 1 Rodas3, 2 Eq. 2, 3 Seulex family.  Returns the
+// cell status; y and h_io are updated as for a chemistry cell.
+int oracle_controller_test(int method, int n, const double* lam, double bound, double* y, double dt, double rtol,
+                           double atol, const OracleOpts* o, double* h_io, double* trace, int cap,
+                           int32_t* nattempts, int32_t* steps, int32_t* rejects) {
+  const DiagSystem sys{n, lam, bound};
+  std::vector<Attempt> tr;
+  CellResult r = method == 3 ? integrate_seulex(sys, dt, rtol, atol, *o, y, h_io, nullptr, &tr)
+                             : integrate_ros(sys, method, dt, rtol, atol, *o, y, h_io, nullptr, &tr);
+  for (int a = 0; a < (int)tr.size() && a < cap; ++a) {
+    trace[4 * a + 0] = tr[a].h;
+    trace[4 * a + 1] = tr[a].err;
+    trace[4 * a + 2] = tr[a].outcome;
+    trace[4 * a + 3] = tr[a].k;
+  }
+  *nattempts = (int32_t)tr.size();
+  *steps = r.steps;
+  *rejects = r.rejects;
+  return r.status;
 }
 
 // Fixed-step integration of a built-in test problem; errout gets the embedded
