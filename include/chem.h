@@ -62,6 +62,8 @@ typedef struct chem_mech_desc {
   const double* eff;   /* [R][K] third-body efficiencies (ignored for type 0) */
   const double* troe;  /* [R][4] alpha, T***, T*, T** (type 2 only) */
   const double* low;   /* [R][3] lnA0, b0, theta0 of k0 (type 2 only) */
+  int32_t n_elements;  /* E >= 0; 0 skips the element-balance check */
+  const int32_t* elem; /* [K][E] atoms of each element per molecule (read when E > 0) */
 } chem_mech_desc;
 
 typedef struct chem_mech chem_mech; /* opaque, library-owned */
@@ -121,10 +123,14 @@ typedef struct chem_options {
                                 (chem_integrate only; the adjoint rejects it) */
 } chem_options;
 
-/* Validates (element balance is not required; indices, cp > 0 on
- * [200, 6000] K, positive W) and uploads the mechanism; *out receives a handle
- * to release with chem_free_mechanism.  EUNSUPPORTED if K > 254 or a reaction
- * has more than 8 non-unit efficiencies. */
+/* Validates and uploads the mechanism; *out receives a handle to release with
+ * chem_free_mechanism.  Checks (CHEM_EINVAL, message naming the item): species
+ * indices in range, positive finite W, finite NASA-7 data with cp > 0 on
+ * [200, 6000] K, and, when n_elements > 0, that every reaction conserves each
+ * element (sum over reactant molecules of elem = sum over product molecules;
+ * the third body M is not a species), as every elementary reaction of the
+ * Chemkin form of section 2.1 does.  EUNSUPPORTED if K > 254 or a reaction has
+ * more than 8 non-unit efficiencies. */
 int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out);
 void chem_free_mechanism(chem_mech* mech);
 
@@ -152,6 +158,15 @@ int chem_set_arrhenius(chem_mech* mech, const double* lnA, const double* b, cons
 int chem_integrate(const chem_mech* mech, int64_t ncells, int64_t ld, double* state, double* h, double p,
                    double dt, double rtol, double atol, const chem_options* opt, int32_t* steps,
                    int32_t* rejects, int32_t* status, void* stream);
+
+/* Number of cells that ended with a nonzero status (CHEM_CELL_*) in the last
+ * chem_integrate or chem_integrate_adjoint call on this mechanism that
+ * integrated at least one cell (counted on the device also when the call's
+ * status pointer was NULL; cells mapped onto a failed reference cell count).
+ * Section 2.1: every cell's ODE is solved independently, so a failed cell
+ * never fails the call; this reports how many did.  Copies one device counter
+ * into *out (host) and synchronises the stream. */
+int chem_failed_count(const chem_mech* mech, int64_t* out, void* stream);
 
 /* Discrete adjoint of chem_integrate (not in the paper): integrates forward
  * recording the accepted step sizes and a checkpoint every checkpoint_every
@@ -196,6 +211,19 @@ int chem_rhs(const chem_mech* mech, int64_t ncells, int64_t ld, const double* st
 int chem_jacobian(const chem_mech* mech, int64_t ncells, int64_t ld, const double* state, double p, double* J,
                   double* f, void* stream);
 int chem_lu_solve(int64_t nmat, int32_t n, const double* A, double* b, int32_t* info, void* stream);
+
+/* chem_lu_factor: the factorisation alone, in LAPACK getrf's form (section 2.3
+ * replaces OpenFOAM's LU with LAPACK's): for each A (device [nmat][n][n]
+ * row-major, not modified), LU (device [nmat][n][n] row-major, distinct from A)
+ * receives P A = L U with the unit-lower L below the diagonal and U on and
+ * above it, and ipiv (device [nmat][n] int32, 0-based like
+ * scipy.linalg.lu_factor) the row interchanged with row k at step k.  The
+ * pivot of step k is the row of largest |a| among rows k..n-1 in getrf's
+ * current order, the first of them on exact ties (idamax).  info as for
+ * chem_lu_solve; when info != 0, LU and ipiv are unspecified.  n <= 256 (n > 64
+ * synchronises the stream). */
+int chem_lu_factor(int64_t nmat, int32_t n, const double* A, double* LU, int32_t* ipiv, int32_t* info,
+                   void* stream);
 
 /* Times the launch variants on the given input (on a scratch copy; the
  * caller's arrays are not modified) and stores the fastest as the default of

@@ -30,7 +30,7 @@ class _Desc(C.Structure):
     _fields_ = [("n_species", C.c_int32), ("n_reactions", C.c_int32), ("W", C.c_void_p),
                 ("nasa7", C.c_void_p), ("rtype", C.c_void_p), ("reac", C.c_void_p), ("prod", C.c_void_p),
                 ("lnA", C.c_void_p), ("b", C.c_void_p), ("theta", C.c_void_p), ("eff", C.c_void_p),
-                ("troe", C.c_void_p), ("low", C.c_void_p)]
+                ("troe", C.c_void_p), ("low", C.c_void_p), ("n_elements", C.c_int32), ("elem", C.c_void_p)]
 
 
 class RefMap(C.Structure):
@@ -91,6 +91,8 @@ def lib():
         L.chem_rhs.argtypes = [vp, i64, i64, vp, d, vp, vp]
         L.chem_jacobian.argtypes = [vp, i64, i64, vp, d, vp, vp, vp]
         L.chem_lu_solve.argtypes = [i64, i32, vp, vp, vp, vp]
+        L.chem_lu_factor.argtypes = [i64, i32, vp, vp, vp, vp, vp]
+        L.chem_failed_count.argtypes = [vp, C.POINTER(i64), vp]
         L.chem_autotune.argtypes = [vp, i64, i64, vp, vp, d, d, d, d, vp, vp, vp]
         L.chem_set_adjoint_record_budget.argtypes = [C.c_uint64]
         _lib = L
@@ -129,9 +131,13 @@ class Mechanism:
                             b=f64(mech["b"]), theta=f64(mech["theta"]), eff=f64(mech["eff"]),
                             troe=f64(mech["troe"]), low=f64(mech["low"]))
         a = self._arrays
+        if mech.get("elem") is not None:
+            a["elem"] = i32(mech["elem"])
         desc = _Desc(int(mech["n_species"]), int(mech["n_reactions"]),
                      *(a[k].ctypes.data for k in ("W", "nasa7", "rtype", "reac", "prod", "lnA", "b", "theta",
-                                                  "eff", "troe", "low")))
+                                                  "eff", "troe", "low")),
+                     int(a["elem"].shape[1]) if "elem" in a else 0,
+                     a["elem"].ctypes.data if "elem" in a else None)
         h = C.c_void_p()
         _check(lib().chem_load_mechanism(C.byref(desc), C.byref(h)))
         self._h = h
@@ -208,33 +214,47 @@ class IntegrateFn(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, state0, lnA, b, theta, mech, p, dt, rtol, atol, options, checkpoint_every):
+    def forward(ctx, state0, lnA, b, theta, mech, p, dt, rtol, atol, options, checkpoint_every, max_tape):
         mech.set_arrhenius(lnA.detach().contiguous(), b.detach().contiguous(), theta.detach().contiguous())
         st = state0.detach().clone().contiguous()
         h = torch.zeros(st.shape[1], dtype=torch.float64, device=st.device)
         status = torch.empty(st.shape[1], dtype=torch.int32, device=st.device)
         integrate(mech, st, h, p, dt, rtol, atol, options=options, status=status)
+        _raise_failed(status, "forward integration")
         ctx.save_for_backward(state0.detach(), lnA.detach(), b.detach(), theta.detach())
-        ctx.cfg = (mech, p, dt, rtol, atol, options, checkpoint_every)
-        ctx.status = status
+        ctx.cfg = (mech, p, dt, rtol, atol, options, checkpoint_every, max_tape)
         return st
 
     @staticmethod
     def backward(ctx, gout):
         state0, lnA, b, theta = ctx.saved_tensors
-        mech, p, dt, rtol, atol, options, ck = ctx.cfg
+        mech, p, dt, rtol, atol, options, ck, mt = ctx.cfg
         mech.set_arrhenius(lnA.contiguous(), b.contiguous(), theta.contiguous())
         h = torch.zeros(state0.shape[1], dtype=torch.float64, device=state0.device)
         _, lam0, grad, _, status = integrate_adjoint(mech, state0.contiguous(), h, p, dt, rtol, atol,
-                                                     gout.contiguous(), options=options, checkpoint_every=ck)
-        ctx.adjoint_status = status
-        return lam0, grad[0], grad[1], grad[2], None, None, None, None, None, None, None
+                                                     gout.contiguous(), options=options, checkpoint_every=ck,
+                                                     max_tape=mt)
+        # a cell without a complete reverse sweep (TAPE_FULL, or a failed
+        # forward) would contribute lambda0 = lambda_final and no parameter
+        # gradient: refuse to return such gradients
+        _raise_failed(status, "adjoint")
+        return lam0, grad[0], grad[1], grad[2], None, None, None, None, None, None, None, None
+
+
+def _raise_failed(status, what):
+    bad = status != 0
+    if bool(bad.any()):
+        codes = torch.unique(status[bad]).tolist()
+        raise ChemError(-1, f"{what}: {int(bad.sum())} cells ended with status "
+                        f"{', '.join(CELL_STATUS.get(c, str(c)) for c in codes)}")
 
 
 def integrate_diff(mech: Mechanism, state0, lnA, b, theta, p, dt, rtol=1e-6, atol=1e-10,
-                   options: Options | None = None, checkpoint_every=8):
-    """Differentiable integration over one CFD step (see IntegrateFn)."""
-    return IntegrateFn.apply(state0, lnA, b, theta, mech, p, dt, rtol, atol, options, checkpoint_every)
+                   options: Options | None = None, checkpoint_every=8, max_tape=0):
+    """Differentiable integration over one CFD step (see IntegrateFn).  max_tape
+    bounds the accepted steps per cell that the backward pass records (0 =
+    4096); forward and backward raise ChemError if any cell fails."""
+    return IntegrateFn.apply(state0, lnA, b, theta, mech, p, dt, rtol, atol, options, checkpoint_every, max_tape)
 
 
 def rhs(mech: Mechanism, state, p):
@@ -265,6 +285,24 @@ def lu_solve(A, b):
     return x, info
 
 
+def lu_factor(A):
+    """Batched getrf (A [nmat, n, n]); returns (LU, ipiv (0-based), info)."""
+    _dev(A, torch.float64, "A")
+    nmat, n, _ = A.shape
+    LU = torch.empty_like(A)
+    ipiv = torch.empty((nmat, n), dtype=torch.int32, device=A.device)
+    info = torch.empty(nmat, dtype=torch.int32, device=A.device)
+    _check(lib().chem_lu_factor(nmat, n, _ptr(A), _ptr(LU), _ptr(ipiv), _ptr(info), _stream()))
+    return LU, ipiv, info
+
+
+def failed_count(mech: Mechanism) -> int:
+    """chem_failed_count: cells with a nonzero status in the mechanism's last integration."""
+    out = C.c_int64()
+    _check(lib().chem_failed_count(mech.handle, C.byref(out), _stream()))
+    return out.value
+
+
 def autotune(mech: Mechanism, state, h, p, dt, rtol=1e-6, atol=1e-10):
     """Times the launch variants on (a scratch copy of) the input; returns (variant, ms)."""
     _dev(state, torch.float64, "state")
@@ -285,4 +323,5 @@ def set_adjoint_record_budget(nbytes: int) -> None:
 
 EXPORTED = ["chem_load_mechanism", "chem_free_mechanism", "chem_max_n", "chem_mech_sizes", "chem_set_arrhenius",
             "chem_integrate", "chem_integrate_adjoint", "chem_set_adjoint_record_budget", "chem_rhs",
-            "chem_jacobian", "chem_lu_solve", "chem_autotune", "chem_last_error"]
+            "chem_jacobian", "chem_lu_solve", "chem_lu_factor", "chem_failed_count", "chem_autotune",
+            "chem_last_error"]

@@ -90,8 +90,11 @@ __global__ __launch_bounds__(max_threads<NP>()) void k_integrate_sx(IntArgs a) {
   }
 }
 
-__global__ void k_reset(int* q) {
-  if (threadIdx.x == 0) *q = 0;
+__global__ void k_reset(int* q, unsigned long long* failed) {
+  if (threadIdx.x == 0) {
+    if (q) *q = 0;
+    if (failed) *failed = 0ull;
+  }
 }
 
 template <int NP>
@@ -143,6 +146,32 @@ __global__ __launch_bounds__(256) void k_lu_solve(int64_t nmat, int n, const dou
   const double bi = lane < n ? b[(size_t)mi * n + lane] : 0.0;
   const double x = lu_solve<NP>(row, n, lane, src, myrdiag, bi);
   if (lane < n) b[(size_t)mi * n + lane] = x;
+}
+
+// getrf of each matrix: LU in LAPACK's layout (rows in pivot order) and ipiv.
+template <int NP>
+__global__ __launch_bounds__(256) void k_lu_factor(int64_t nmat, int n, const double* A, double* LU, int32_t* ipiv,
+                                                   int32_t* info) {
+  __shared__ int slots[4][64];
+  const int wv = threadIdx.x / WAVE;
+  const int64_t mi = (int64_t)blockIdx.x * (blockDim.x / WAVE) + wv;
+  if (mi >= nmat) return;
+  const int lane = lane_id();
+  double row[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) row[j] = (lane < n && j < n) ? A[((size_t)mi * n + lane) * n + j] : 0.0;
+  int mystep, myipiv = 0;
+  double myrdiag;
+  const int rc = lu_factor<NP>(row, n, lane, mystep, myrdiag, false, &myipiv);
+  if (lane == 0) info[mi] = rc;
+  if (rc) return;  // some rows never became pivots: no permutation to apply
+  permute_rows<NP>(row, n, lane, mystep, myrdiag, slots[wv]);
+  if (lane < n) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j)
+      if (j < n) LU[((size_t)mi * n + lane) * n + j] = row[j];
+    ipiv[(size_t)mi * n + lane] = myipiv;
+  }
 }
 
 // ---------------------------------------------------------------- workgroup path (64 < N <= 256)
@@ -231,7 +260,7 @@ __global__ __launch_bounds__(WG) void k_rhs_jac_wg(IntArgs a, WgTerms tl, double
 }
 
 __global__ __launch_bounds__(WG) void k_lu_wg(int64_t nmat, int n, const double* A, double* b, int32_t* info,
-                                              double* scratch, int NP) {
+                                              double* scratch, int NP, double* LU, int32_t* ipiv) {
   extern __shared__ __align__(16) uint8_t lds[];
   const WgWs w = make_wg_ws((double*)lds, 0, NP);
   double* Mx = scratch + (size_t)blockIdx.x * NP * NP;
@@ -244,7 +273,10 @@ __global__ __launch_bounds__(WG) void k_lu_wg(int64_t nmat, int n, const double*
     __syncthreads();
     const int rc = wg_lu(w, Mx, NP);
     if (t == 0) info[mi] = rc;
-    if (rc == 0) {
+    if (LU) {  // factors only: Mx holds them in LAPACK's layout (rows interchanged)
+      for (int idx = t; idx < n * n; idx += WG) LU[(size_t)mi * n * n + idx] = Mx[(size_t)(idx / n) * NP + idx % n];
+      if (t < n) ipiv[(size_t)mi * n + t] = w.piv[t];
+    } else if (rc == 0) {
       const double x = wg_solve(w, Mx, NP, t < n ? b[(size_t)mi * n + t] : 0.0);
       if (t < n) b[(size_t)mi * n + t] = x;
     }
@@ -361,7 +393,7 @@ __global__ void k_refmap_mark(double* st, int64_t ld, int64_t n, int N, double d
 
 __global__ void k_refmap_apply(double* st, int64_t ld, int64_t n, int N, const int32_t* ref_of,
                                const unsigned long long* rm, double* h, int32_t* steps, int32_t* rejects,
-                               int32_t* status) {
+                               int32_t* status, unsigned long long* failed) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const int32_t r = ref_of[c];
@@ -374,7 +406,8 @@ __global__ void k_refmap_apply(double* st, int64_t ld, int64_t n, int N, const i
   h[c] = h[r];
   if (steps) steps[c] = 0;
   if (rejects) rejects[c] = 0;
-  if (status) status[c] = status[r];
+  status[c] = status[r];
+  if (failed && status[r] != 0) atomicAdd(failed, 1ull);
 }
 
 }  // namespace
@@ -414,6 +447,9 @@ struct chem_mech {
   int32_t* perm = nullptr;  // device: internal -> descriptor reaction index
   std::vector<int32_t> h_perm;
   int* queue = nullptr;     // device work cursor
+  unsigned long long* failed = nullptr;  // device: cells of the last integration with a nonzero status
+  int32_t* st_buf = nullptr;  // library status array when the caller passes none (reference mapping)
+  int64_t st_cap = 0;
   int32_t* order = nullptr; // device cost order of the queue
   int64_t order_cap = 0;
   int* order_cnt = nullptr; // device bucket counters and cursors [64], queue length [1]
@@ -530,7 +566,8 @@ int launch_integrate_wg(chem_mech* m, const IntArgs& a0, hipStream_t s) {
                             : (a.prof ? k_integrate_wg<true> : k_integrate_wg<false>);
   HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   a.queue = m->queue;
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, m->queue);
+  a.failed = m->failed;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, m->queue, m->failed);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), lds, s, a, wg_terms(m), m->wg_scr, m->wg_np);
   HIPCHK(hipGetLastError());
   return 0;
@@ -568,12 +605,13 @@ int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStrea
       const int64_t need = (a.ncells + wpb - 1) / wpb;
       grid = (int)std::min<int64_t>((int64_t)m->ncu * occ * std::max(1, v.grid_mult), need);
       a.queue = m->queue;
-      hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, m->queue);
-      HIPCHK(hipGetLastError());
     } else {
       a.queue = nullptr;
       grid = (int)((a.ncells + wpb - 1) / wpb);
     }
+    a.failed = m->failed;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.queue ? m->queue : nullptr, m->failed);
+    HIPCHK(hipGetLastError());
     if (grid > 0) {
       hipLaunchKernelGGL(kern, dim3(grid), dim3(wpb * WAVE), lds, s, a);
       HIPCHK(hipGetLastError());
@@ -612,7 +650,7 @@ int launch_refmap_apply(chem_mech* m, const int32_t* ref_of, double* state, int6
                         int32_t* steps, int32_t* rejects, int32_t* status, hipStream_t s) {
   const int nb = (int)((ncells + 255) / 256);
   hipLaunchKernelGGL(k_refmap_apply, dim3(nb), dim3(256), 0, s, state, ld, ncells, m->d.N, ref_of, m->rm_buf, h,
-                     steps, rejects, status);
+                     steps, rejects, status, m->failed);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -668,6 +706,24 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   for (int r = 0; r < R; ++r) {
     if (desc->rtype[r] == 0) ++R0;
     if (desc->rtype[r] <= 1) ++R1;
+  }
+  if (desc->n_elements < 0 || (desc->n_elements > 0 && !desc->elem))
+    return fail(CHEM_EINVAL, "n_elements must be >= 0, with an elem array when > 0");
+  if (desc->n_elements > 0) {
+    // every reaction conserves each element (a third body is not a species)
+    const int E = desc->n_elements;
+    for (int r = 0; r < R; ++r) {
+      for (int e = 0; e < E; ++e) {
+        long long bal = 0;
+        for (int s2 = 0; s2 < 3; ++s2) {
+          const int a = desc->reac[3 * r + s2], b = desc->prod[3 * r + s2];
+          if (a >= 0 && a < K) bal -= desc->elem[(size_t)a * E + e];
+          if (b >= 0 && b < K) bal += desc->elem[(size_t)b * E + e];
+        }
+        if (bal != 0)
+          return fail(CHEM_EINVAL, "reaction " + std::to_string(r) + " does not conserve element " + std::to_string(e));
+      }
+    }
   }
   if (R > R0 && !desc->eff) return fail(CHEM_EINVAL, "third-body reactions need efficiencies");
   if (R > R1 && (!desc->troe || !desc->low)) return fail(CHEM_EINVAL, "Troe reactions need troe and low data");
@@ -885,8 +941,11 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
     return cleanup(CHEM_EHIP, "upload failed");
   if (hipMemcpy(m->blob, blob.data(), blob.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->nasa, nasa.data(), 8 * nasa.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      (R > 0 && hipMemcpy(m->perm, order.data(), 4 * (size_t)R, hipMemcpyHostToDevice) != hipSuccess))
+      (R > 0 && hipMemcpy(m->perm, order.data(), 4 * (size_t)R, hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemset(m->queue, 0, 64) != hipSuccess)
     return cleanup(CHEM_EHIP, "upload failed");
+  // the failed-cell counter shares the 64-byte queue allocation (the cursor is its first word)
+  m->failed = reinterpret_cast<unsigned long long*>(reinterpret_cast<uint8_t*>(m->queue) + 8);
   *out = m;
   return CHEM_OK;
 }
@@ -905,6 +964,7 @@ void chem_free_mechanism(chem_mech* m) {
   hipFree(m->order_cnt);
   hipFree(m->rm_buf);
   hipFree(m->rm_flags);
+  hipFree(m->st_buf);
   hipFree(m->wg_gptr);
   hipFree(m->wg_grp);
   hipFree(m->wg_term);
@@ -985,7 +1045,7 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
     return fail(CHEM_EINVAL, "need p > 0, dt > 0, rtol >= 0, atol >= 0");
   if (ncells > (int64_t)INT32_MAX) return fail(CHEM_EUNSUPPORTED, "more than 2^31-1 cells");
   IntArgs a = base_args(m);
-  if (fill_common(m, opt, a)) return CHEM_EINVAL;
+  if (const int rc = fill_common(m, opt, a)) return rc;
   a.state = state;
   a.ld = ld;
   a.ncells = ncells;
@@ -1017,6 +1077,18 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
     }
   }
   int32_t* ref_of = rmp ? (rmp->ref_of ? rmp->ref_of : m->rm_flags) : nullptr;
+  if (rmp && !status) {  // mapped cells copy the reference's status, so one is always kept
+    if (m->st_cap < ncells) {
+      hipFree(m->st_buf);
+      m->st_buf = nullptr;
+      m->st_cap = 0;
+      if (hipMalloc(&m->st_buf, sizeof(int32_t) * ncells) != hipSuccess)
+        return fail(CHEM_ENOMEM, "status buffer allocation failed");
+      m->st_cap = ncells;
+    }
+    status = m->st_buf;
+    a.status = status;
+  }
   const bool queued = ordered || rmp;
   if (queued && m->order_cap < ncells) {
     hipFree(m->order);
@@ -1050,10 +1122,12 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
              (uintptr_t)rejects, (uintptr_t)status, (uintptr_t)s, (uintptr_t)v.wpb, (uintptr_t)v.grid_mult,
              (uintptr_t)ordered, (uintptr_t)m->order, (uintptr_t)m->wg_scr, (uintptr_t)m->order_cnt,
              (uintptr_t)(rmp != nullptr), (uintptr_t)(rmp ? rmp->weight : nullptr), (uintptr_t)ref_of,
-             (uintptr_t)m->rm_buf};
-    double dv[10] = {p, dt, rtol, atol, (double)(opt ? opt->method : 0), (double)a.jac_fd, (double)a.lu_nopiv,
-                     rmp ? rmp->z0 : 0.0, rmp ? rmp->z_max : 0.0, rmp ? rmp->dT : 0.0};
-    for (double x : dv) {
+             (uintptr_t)m->rm_buf, (uintptr_t)a.prof, (uintptr_t)a.ctl.max_steps, (uintptr_t)v.persistent};
+    // every value baked into the captured kernel arguments is part of the key
+    double dv[14] = {p, dt, rtol, atol, (double)(opt ? opt->method : 0), (double)a.jac_fd, (double)a.lu_nopiv,
+                     rmp ? rmp->z0 : 0.0, rmp ? rmp->z_max : 0.0, rmp ? rmp->dT : 0.0,
+                     a.ctl.fac_safe, a.ctl.fac_min, a.ctl.fac_max, a.ctl.h_min};
+    for (double x : dv) {  // bit patterns (distinguishes -0.0 and NaN payloads too)
       uint64_t u;
       std::memcpy(&u, &x, 8);
       key.v.push_back((uintptr_t)u);
@@ -1124,38 +1198,68 @@ int chem_jacobian(const chem_mech* m, int64_t ncells, int64_t ld, const double* 
   });
 }
 
+// Workgroup LU (64 < n <= 256): one matrix per 256-thread workgroup, an
+// NP x NP scratch slot each; solves (LU == NULL) or writes the factors.
+static int lu_wg_launch(int64_t nmat, int32_t n, const double* A, double* b, int32_t* info, double* LU,
+                        int32_t* ipiv, void* stream) {
+  const int NP = ((n + 15) / 16) * 16;
+  int dev = 0, ncu = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  const int grid = (int)std::min<int64_t>(nmat, std::max(ncu, 1));
+  double* scr = nullptr;
+  if (hipMalloc(&scr, sizeof(double) * (size_t)grid * NP * NP) != hipSuccess)
+    return fail(CHEM_ENOMEM, "LU scratch allocation failed");
+  const size_t lds = (size_t)wg_ws_doubles(0, NP) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_lu_wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_lu_wg, dim3(grid), dim3(WG), lds, (hipStream_t)stream, nmat, n, A, b, info, scr, NP, LU,
+                       ipiv);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  hipFree(scr);
+  if (e != hipSuccess) return fail(CHEM_EHIP, std::string("workgroup LU: ") + hipGetErrorString(e));
+  return CHEM_OK;
+}
+
 int chem_lu_solve(int64_t nmat, int32_t n, const double* A, double* b, int32_t* info, void* stream) {
   if (nmat < 0 || n < 1) return fail(CHEM_EINVAL, "need nmat >= 0 and n >= 1");
   if (nmat == 0) return CHEM_OK;
   if (!A || !b || !info) return fail(CHEM_EINVAL, "null argument");
-  if (n > 64) {
-    if (n > 256) return fail(CHEM_EUNSUPPORTED, "n > 256");
-    // workgroup LU: one matrix per 256-thread workgroup, NP x NP scratch each
-    const int NP = ((n + 15) / 16) * 16;
-    int dev = 0, ncu = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    const int grid = (int)std::min<int64_t>(nmat, std::max(ncu, 1));
-    double* scr = nullptr;
-    if (hipMalloc(&scr, sizeof(double) * (size_t)grid * NP * NP) != hipSuccess)
-      return fail(CHEM_ENOMEM, "LU scratch allocation failed");
-    const size_t lds = (size_t)wg_ws_doubles(0, NP) * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void*)k_lu_wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(k_lu_wg, dim3(grid), dim3(WG), lds, (hipStream_t)stream, nmat, n, A, b, info, scr, NP);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
-    hipFree(scr);
-    if (e != hipSuccess) return fail(CHEM_EHIP, std::string("workgroup LU: ") + hipGetErrorString(e));
-    return CHEM_OK;
-  }
+  if (n > 256) return fail(CHEM_EUNSUPPORTED, "n > 256");
+  if (n > 64) return lu_wg_launch(nmat, n, A, b, info, nullptr, nullptr, stream);
   return with_np(n, [&](auto npc) -> int {
     constexpr int NP = decltype(npc)::value;
     hipLaunchKernelGGL(k_lu_solve<NP>, dim3((nmat + 3) / 4), dim3(256), 0, (hipStream_t)stream, nmat, n, A, b, info);
     HIPCHK(hipGetLastError());
     return 0;
   });
+}
+
+int chem_lu_factor(int64_t nmat, int32_t n, const double* A, double* LU, int32_t* ipiv, int32_t* info,
+                   void* stream) {
+  if (nmat < 0 || n < 1) return fail(CHEM_EINVAL, "need nmat >= 0 and n >= 1");
+  if (nmat == 0) return CHEM_OK;
+  if (!A || !LU || !ipiv || !info) return fail(CHEM_EINVAL, "null argument");
+  if (n > 256) return fail(CHEM_EUNSUPPORTED, "n > 256");
+  if (n > 64) return lu_wg_launch(nmat, n, A, nullptr, info, LU, ipiv, stream);
+  return with_np(n, [&](auto npc) -> int {
+    constexpr int NP = decltype(npc)::value;
+    hipLaunchKernelGGL(k_lu_factor<NP>, dim3((nmat + 3) / 4), dim3(256), 0, (hipStream_t)stream, nmat, n, A, LU,
+                       ipiv, info);
+    HIPCHK(hipGetLastError());
+    return 0;
+  });
+}
+
+int chem_failed_count(const chem_mech* m, int64_t* out, void* stream) {
+  if (!m || !out) return fail(CHEM_EINVAL, "null argument");
+  unsigned long long v = 0;
+  HIPCHK(hipMemcpyAsync(&v, m->failed, sizeof(v), hipMemcpyDeviceToHost, (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  *out = (int64_t)v;
+  return CHEM_OK;
 }
 
 int chem_autotune(chem_mech* m, int64_t ncells, int64_t ld, const double* state, const double* h, double p,

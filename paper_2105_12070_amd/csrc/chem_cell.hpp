@@ -475,20 +475,27 @@ __device__ __forceinline__ double recip(double x) {
   return fma(r, e, r);
 }
 
-// LU with partial pivoting of the row-per-lane matrix.  No rows move: the
-// lane chosen at step k records mystep = k; L multipliers of step k stay in
-// column k of the remaining rows.  The pivot is the first lane whose |a|
-// carries the largest upper 32 bits (sign cleared) among unpivoted rows.
+// LU with partial pivoting of the row-per-lane matrix, with getrf's pivot
+// rule: at step k the pivot is the unpivoted row of largest |a|, exact ties
+// going to the row that comes first in getrf's current row order (the order
+// after the interchanges k <-> pivot of the earlier steps).  No rows move: the
+// lane chosen at step k records mystep = k, and pos tracks where getrf would
+// hold the lane's row.  L multipliers of step k stay in column k of the
+// remaining rows.  |a| is compared as an integer key: the upper 32 bits
+// (sign cleared) by one wave max; only when several lanes share the largest
+// upper half do the lower halves, and then the positions, decide.
 // Steps run in static phases of four: phase P only touches columns >= 4P.
 // Inside a phase the four columns of chunk P rotate through c0..c3 so that
 // the pivot column is always c0; every register index is static.
-// Returns the 1-based step of a zero pivot, or 0.
+// Returns the 1-based step of a zero pivot, or 0.  myipiv (lane k) receives
+// getrf's ipiv[k]: the position the step-k pivot row held before its interchange.
 template <int NP>
 __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep, double& myrdiag,
-                                bool nopiv = false) {
+                                bool nopiv = false, int* myipiv = nullptr) {
   mystep = lane < N ? -1 : (1 << 20);
   myrdiag = 0.0;
   int info = 0;
+  int pos = lane;
 #pragma clang loop unroll(full)
   for (int P = 0; P < NP / 4; ++P) {
     const int k0 = 4 * P;
@@ -498,15 +505,34 @@ __device__ inline int lu_factor(double (&row)[NP], int N, int lane, int& mystep,
     for (int k = k0; k < k1; ++k) {
       const int kk = k - k0;
       const bool elig = mystep < 0;
-      const unsigned hi = (unsigned)(__builtin_bit_cast(unsigned long long, c0) >> 32) & 0x7fffffffu;
-      const unsigned key = elig ? hi : 0u;
+      const unsigned long long mag = __builtin_bit_cast(unsigned long long, c0) & 0x7fffffffffffffffull;
+      const unsigned key = elig ? (unsigned)(mag >> 32) : 0u;
       const unsigned kmax = wave_max_u32(key);
+      unsigned long long cand = ballot(elig && key == kmax);
+      bool sing = kmax == 0u;
+      if (!nopiv && (sing || (cand & (cand - 1)) != 0ull)) {  // wave-uniform: rare tie path
+        const bool c = elig && key == kmax;
+        const unsigned lmax = wave_max_u32(c ? (unsigned)mag : 0u);
+        sing = sing && lmax == 0u;
+        cand = ballot(c && (unsigned)mag == lmax);
+        if ((cand & (cand - 1)) != 0ull) {
+          const bool tie = ((cand >> lane) & 1ull) != 0ull;
+          const int pmin = 63 - (int)wave_max_u32(tie ? (unsigned)(63 - pos) : 0u);
+          cand = ballot(tie && pos == pmin);
+        }
+      }
       // a zero pivot column is recorded and the factorisation runs on with
       // zero multipliers (no early exit keeps the control flow simple)
       // without pivoting (ablation) the pivot is row k itself
-      const bool sing = nopiv ? !(readlane(c0, k) != 0.0) : kmax == 0u;
+      if (nopiv) sing = !(readlane(c0, k) != 0.0);
       if (sing && info == 0) info = k + 1;
-      const int p = sing ? 0 : (nopiv ? k : uniform_int(__builtin_ctzll(ballot(elig && key == kmax))));
+      const int p = sing ? 0 : (nopiv ? k : uniform_int(__builtin_ctzll(cand)));
+      {  // getrf interchanges rows k and pos(p)
+        const int pp = sing ? k : uniform_int(__builtin_amdgcn_readlane(pos, p));
+        if (myipiv && lane == k) *myipiv = pp;
+        const int np = pos == k ? pp : pos;
+        pos = (lane == p && !sing) ? k : np;
+      }
       const double piv = readlane(c0, p);
       const double rp = recip(piv);
       const bool upd = elig && lane != p && !sing;
@@ -793,6 +819,7 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
     if (a.steps) a.steps[c] = steps;
     if (a.rejects) a.rejects[c] = rejects;
     if (a.status) a.status[c] = status;
+    if (a.failed && status != ST_OK) atomicAdd(a.failed, 1ull);
   }
   if (PROF && a.prof && lane < 8) {
     unsigned long long v = 0;

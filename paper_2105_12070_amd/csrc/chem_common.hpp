@@ -91,6 +91,7 @@ struct IntArgs {
   double* tape_y;           // [ncells][max_tape/ckpt + 1][N]
   int max_tape, ckpt;
   unsigned long long* prof; // [ncells][8] per-phase cycle counts, or NULL
+  unsigned long long* failed; // cells that ended with a nonzero status (counter), or NULL
   int jac_fd;               // ablation (instrumented kernel only): finite-difference Jacobian
   int lu_nopiv;             // ablation (instrumented kernel only): LU without pivoting
 };

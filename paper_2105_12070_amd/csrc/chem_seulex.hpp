@@ -184,6 +184,7 @@ __device__ void integrate_cell_sx(const MechView& m, const CellWs& w, const IntA
     if (a.steps) a.steps[c] = steps;
     if (a.rejects) a.rejects[c] = rejects;
     if (a.status) a.status[c] = status;
+    if (a.failed && status != ST_OK) atomicAdd(a.failed, 1ull);
   }
   if (PROF && a.prof && lane < 8) {
     unsigned long long v = 0;
@@ -341,6 +342,7 @@ __device__ void wg_integrate_cell_sx(const MechView& m, const WgWs& w, const WgT
     if (a.steps) a.steps[c] = steps;
     if (a.rejects) a.rejects[c] = rejects;
     if (a.status) a.status[c] = status;
+    if (a.failed && status != ST_OK) atomicAdd(a.failed, 1ull);
   }
   if (PROF && a.prof && t < 8) {
     unsigned long long v = 0;

@@ -931,6 +931,7 @@ __device__ inline void wg_integrate_cell(const MechView& m, const WgWs& w, const
     if (a.steps) a.steps[c] = steps;
     if (a.rejects) a.rejects[c] = rejects;
     if (a.status) a.status[c] = status;
+    if (a.failed && status != ST_OK) atomicAdd(a.failed, 1ull);
   }
   if (PROF && t < 8) {
     unsigned long long v = 0;

@@ -76,3 +76,34 @@ def test_mechanism_validation_on_host(L):
     big["n_species"] = 300
     with pytest.raises(chem.ChemError, match="EUNSUPPORTED"):
         chem.Mechanism(big)
+
+
+def test_element_balance_is_validated_on_host(L):
+    """A reaction that does not conserve an element is rejected before any
+    device work; a mechanism without element data skips the check."""
+    from paper_2105_12070_amd import chem
+    from paper_2105_12070_amd.inputs import WORKLOADS
+    m = WORKLOADS["c2_54sp"].mechanism()
+    assert m["elem"].shape == (54, 4)
+    bad = dict(m)
+    bad["prod"] = m["prod"].copy()
+    r = int(np.nonzero(m["rtype"] == 0)[0][5])
+    bad["prod"][r] = m["prod"][r][::-1]  # same molecules in other slots: still balanced
+    try:  # passes validation (without a GPU the upload then fails with another code)
+        chem.Mechanism(bad)
+    except chem.ChemError as e:
+        assert e.code != -1, str(e)
+    # swapping a product for another species of different composition breaks balance
+    k = int(bad["prod"][r][-1] if bad["prod"][r][-1] >= 0 else bad["prod"][r][0])
+    other = int(np.nonzero(np.any(m["elem"] != m["elem"][k], axis=1))[0][0])
+    bad["prod"] = bad["prod"].copy()
+    bad["prod"][r][bad["prod"][r] == k] = other
+    with pytest.raises(chem.ChemError, match="does not conserve element"):
+        chem.Mechanism(bad)
+    # without element data the check is skipped
+    skip = dict(bad)
+    skip["elem"] = None
+    try:
+        chem.Mechanism(skip)
+    except chem.ChemError as e:
+        assert e.code != -1, str(e)

@@ -328,3 +328,24 @@ def test_adjoint_empty_and_errors(chem):
     with pytest.raises(chem.ChemError):
         chem.integrate_adjoint(m, s1, torch.zeros(4, dtype=torch.float64, device=DEV), w.p_pa, w.dt, w.rtol,
                                w.atol, torch.zeros_like(s1), checkpoint_every=3, max_tape=10)
+
+
+def test_autograd_refuses_incomplete_sweeps(chem):
+    """With a tape shorter than the cells' step counts the reverse sweep is
+    incomplete (TAPE_FULL): backward() raises instead of returning lambda0 =
+    lambda_final and zero parameter gradients for those cells; a failed
+    forward integration raises in forward()."""
+    w = WORKLOADS["c1_10sp"]
+    mech = w.mechanism()
+    st0 = np.ascontiguousarray(w.states(mech)[:, :64])
+    m = chem.Mechanism(mech)
+    s0 = torch.tensor(st0, device=DEV, requires_grad=True)
+    prm = [torch.tensor(mech[k], device=DEV, requires_grad=True) for k in ("lnA", "b", "theta")]
+    out = chem.integrate_diff(m, s0, *prm, w.p_pa, w.dt, w.rtol, w.atol, checkpoint_every=2, max_tape=4)
+    with pytest.raises(chem.ChemError, match="TAPE_FULL"):
+        out.sum().backward()
+    bad = st0.copy()
+    bad[0, 5] = -1.0
+    with pytest.raises(chem.ChemError, match="NONFINITE"):
+        chem.integrate_diff(m, torch.tensor(bad, device=DEV, requires_grad=True), *prm, w.p_pa, w.dt, w.rtol,
+                            w.atol)

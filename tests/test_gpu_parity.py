@@ -1,11 +1,11 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
 Tolerances:
-  * integration at rtol 1e-10, atol 1e-14: |x_gpu - x_ref| <= 1e-8 |x_ref| +
-    100 atol per component (T and every Y).  Relative 1e-8 is the bar stated
-    for this path; trace species are controlled by atol, and one flipped
-    accept/reject decision moves them by ~1e-13 absolute in the oracle itself,
-    hence the absolute floor of 100 atol;
+  * integration at rtol 1e-10, atol 1e-16: |x_gpu - x_ref| <= 1e-8 |x_ref| +
+    1e-14 per component (T and every Y).  Relative 1e-8 is the bar stated for
+    this path; the absolute floor 1e-14 covers trace species, which atol =
+    1e-16 resolves to ~1e-16 (measured on the oracle itself: one flipped
+    accept/reject decision moves a run by at most 0.24 of this bound);
   * integration at the metric setting (rtol 1e-6, atol 1e-10): accept/reject
     decisions taken with err close to 1 may flip on rounding, after which two
     valid runs differ by their global error.  Measured on the same 18 cells,
@@ -139,14 +139,16 @@ def test_jacobian_matches_oracle(chem, dev, name):
 
 
 # ------------------------------------------------------ integration parity
-TIGHT_RTOL, TIGHT_ATOL = 1e-10, 1e-14
+TIGHT_RTOL, TIGHT_ATOL = 1e-10, 1e-16
+TIGHT_FLOOR = 1e-14
 
 
 def _tight_check(got, ref, tag):
     dev_ = np.abs(got - ref)
-    ok = dev_ <= 1e-8 * np.abs(ref) + 100 * TIGHT_ATOL
-    rel = dev_ / (np.abs(ref) + 100 * TIGHT_ATOL)
-    say(f"[{tag}] max rel dev {rel.max():.3e} median {np.median(rel):.3e}")
+    bound = 1e-8 * np.abs(ref) + TIGHT_FLOOR
+    ok = dev_ <= bound
+    rel = dev_ / bound
+    say(f"[{tag}] max dev / bound {rel.max():.3e} median {np.median(rel):.3e}")
     assert np.all(ok), (tag, np.argwhere(~ok)[:5], rel.max())
 
 
@@ -166,12 +168,12 @@ def test_integrate_parity_c1_tight(chem, dev):
     same = (steps[idx] == rs) & (rej[idx] == rr)
     say(f"[c1 tight] cells with identical (steps, rejects): {same.mean():.3f}")
     assert same.mean() >= 0.9
-    assert np.all(np.abs(got[:, idx][:, same] - ref[:, same]) <= 1e-8 * np.abs(ref[:, same]) + 10 * TIGHT_ATOL)
 
 
 @pytest.mark.parametrize("name", ["c2_54sp", "c4_adj"])
 def test_integrate_parity_large_mech_tight(chem, dev, name):
-    """54- and 53-species mechanisms, 70 cells (ragged over 4-cell workgroups), rtol 1e-10."""
+    """54- and 53-species mechanisms, 70 cells (ragged over 4-cell workgroups), rtol 1e-10, over a short
+    dt (the full flow step of these configurations is tested in test_gpu_tight.py)."""
     w, mech = mech_of(name)
     st0 = w.states(mech, 70)
     dt, rtol, atol = 1e-8, TIGHT_RTOL, TIGHT_ATOL
@@ -184,7 +186,6 @@ def test_integrate_parity_large_mech_tight(chem, dev, name):
     _tight_check(got[:, idx], ref, f"{name} tight")
     same = (steps[idx] == rs) & (rej[idx] == rr)
     say(f"[{name} tight] cells with identical (steps, rejects): {same.mean():.3f}")
-    assert np.all(np.abs(got[:, idx][:, same] - ref[:, same]) <= 1e-8 * np.abs(ref[:, same]) + 10 * TIGHT_ATOL)
 
 
 def test_integrate_full_size_c2_metric(chem, dev):
