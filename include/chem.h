@@ -159,9 +159,28 @@ int chem_integrate(const chem_mech* mech, int64_t ncells, int64_t ld, double* st
                    double dt, double rtol, double atol, const chem_options* opt, int32_t* steps,
                    int32_t* rejects, int32_t* status, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * integration of chem_integrate, same arguments, same kernels and the same
+ * results bit for bit, with every scratch buffer it needs (the persistent
+ * work cursor, the cost-order bucket counters and the cost-ordered queue) in a
+ * 2 MiB device array of the library, one per GPU, held until the process ends
+ * (its address is looked up once per device by chem_load_mechanism).  No
+ * device memory is allocated or freed.  Limits: N <= 64 (CHEM_EUNSUPPORTED
+ * above: the workgroup path needs per-workgroup matrices); a cost-ordered
+ * queue (opt->cost_order with steps) of at most 524,032 cells (CHEM_EINVAL
+ * beyond); no reference-cell mapping (CHEM_EUNSUPPORTED) and no library-owned
+ * graph (opt->use_graph: CHEM_EINVAL).  Every call on one GPU shares that
+ * GPU's array, which keeps the last call's contents: calls that overlap on one
+ * GPU (on different streams, or from several threads) race and must not be
+ * issued. */
+int chem_integrate_noalloc(const chem_mech* mech, int64_t ncells, int64_t ld, double* state, double* h, double p,
+                           double dt, double rtol, double atol, const chem_options* opt, int32_t* steps,
+                           int32_t* rejects, int32_t* status, void* stream);
+
 /* Number of cells that ended with a nonzero status (CHEM_CELL_*) in the last
- * chem_integrate or chem_integrate_adjoint call on this mechanism that
- * integrated at least one cell (counted on the device also when the call's
+ * chem_integrate, chem_integrate_noalloc or chem_integrate_adjoint call on
+ * this mechanism that integrated at least one cell (counted on the device also when the call's
  * status pointer was NULL; cells mapped onto a failed reference cell count).
  * Section 2.1: every cell's ODE is solved independently, so a failed cell
  * never fails the call; this reports how many did.  Copies one device counter

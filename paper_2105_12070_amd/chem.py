@@ -93,6 +93,8 @@ def lib():
         L.chem_lu_solve.argtypes = [i64, i32, vp, vp, vp, vp]
         L.chem_lu_factor.argtypes = [i64, i32, vp, vp, vp, vp, vp]
         L.chem_failed_count.argtypes = [vp, C.POINTER(i64), vp]
+        L.chem_integrate_noalloc.argtypes = [vp, i64, i64, vp, vp, d, d, d, d, C.POINTER(Options), vp, vp, vp,
+                                             vp]
         L.chem_autotune.argtypes = [vp, i64, i64, vp, vp, d, d, d, d, vp, vp, vp]
         L.chem_set_adjoint_record_budget.argtypes = [C.c_uint64]
         _lib = L
@@ -180,6 +182,24 @@ def integrate(mech: Mechanism, state, h, p, dt, rtol=1e-6, atol=1e-10, options: 
     opt = C.byref(options) if options is not None else None
     _check(lib().chem_integrate(mech.handle, nc, ld, _ptr(state), _ptr(h), float(p), float(dt), float(rtol),
                                 float(atol), opt, _ptr(steps), _ptr(rejects), _ptr(status), _stream()))
+
+
+def integrate_noalloc(mech: Mechanism, state, h, p, dt, rtol=1e-6, atol=1e-10, options: Options | None = None,
+                      steps=None, rejects=None, status=None, ncells=None):
+    """chem_integrate_noalloc (no device allocation; scratch in the library's
+    per-GPU array) on an [N, ld] float64 CUDA tensor, in place."""
+    _dev(state, torch.float64, "state")
+    _dev(h, torch.float64, "h")
+    for t, n in ((steps, "steps"), (rejects, "rejects"), (status, "status")):
+        _dev(t, torch.int32, n)
+    N, ld = state.shape
+    if N != mech.N:
+        raise ValueError(f"state has {N} rows, mechanism needs {mech.N}")
+    nc = ld if ncells is None else int(ncells)
+    opt = C.byref(options) if options is not None else None
+    _check(lib().chem_integrate_noalloc(mech.handle, nc, ld, _ptr(state), _ptr(h), float(p), float(dt),
+                                        float(rtol), float(atol), opt, _ptr(steps), _ptr(rejects), _ptr(status),
+                                        _stream()))
 
 
 def integrate_adjoint(mech: Mechanism, state0, h, p, dt, rtol, atol, lambda_final, options: Options | None = None,
@@ -324,4 +344,4 @@ def set_adjoint_record_budget(nbytes: int) -> None:
 EXPORTED = ["chem_load_mechanism", "chem_free_mechanism", "chem_max_n", "chem_mech_sizes", "chem_set_arrhenius",
             "chem_integrate", "chem_integrate_adjoint", "chem_set_adjoint_record_budget", "chem_rhs",
             "chem_jacobian", "chem_lu_solve", "chem_lu_factor", "chem_failed_count", "chem_autotune",
-            "chem_last_error"]
+            "chem_last_error", "chem_integrate_noalloc"]

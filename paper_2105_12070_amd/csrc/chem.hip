@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -412,6 +413,15 @@ __global__ void k_refmap_apply(double* st, int64_t ld, int64_t n, int N, const i
 
 }  // namespace
 
+// Device scratch of chem_integrate_noalloc: the persistent work cursor, the
+// cost-order bucket counters and the cost-ordered queue, for callers that
+// cannot allocate.  One copy per GPU, held until the process ends.  Layout:
+// [0, 4) cursor; [256, 528) bucket counters; [1024, end) queue (int32).
+constexpr size_t NOALLOC_BYTES = (size_t)2 << 20;
+constexpr size_t NOALLOC_CNT_OFF = 256, NOALLOC_ORDER_OFF = 1024;
+constexpr int64_t NOALLOC_MAX_ORDER = (int64_t)((NOALLOC_BYTES - NOALLOC_ORDER_OFF) / sizeof(int32_t));
+static __device__ __align__(256) uint8_t scratch[NOALLOC_BYTES];
+
 // ================================================================ host side
 namespace {
 
@@ -432,6 +442,26 @@ struct Variant {
   int persistent = 1, wpb = 4, grid_mult = 1;
 };
 
+// Device address of `scratch` on the current device, looked up once per
+// device.  The array's name is only a host-side stand-in: kernels get this
+// address, never the name.
+std::mutex g_scr_mu;
+std::map<int, uint8_t*> g_scr_addr;
+
+int noalloc_scratch(int dev, uint8_t** out) {
+  std::lock_guard<std::mutex> lk(g_scr_mu);
+  auto it = g_scr_addr.find(dev);
+  if (it == g_scr_addr.end()) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(CHEM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    it = g_scr_addr.emplace(dev, (uint8_t*)p).first;
+  }
+  *out = it->second;
+  return 0;
+}
+
 struct GraphKey {
   std::vector<uintptr_t> v;
   bool operator<(const GraphKey& o) const { return v < o.v; }
@@ -449,6 +479,7 @@ struct chem_mech {
   int* queue = nullptr;     // device work cursor
   unsigned long long* failed = nullptr;  // device: cells of the last integration with a nonzero status
   int32_t* st_buf = nullptr;  // library status array when the caller passes none (reference mapping)
+  uint8_t* noalloc_scr = nullptr;  // this device's copy of `scratch` (device address)
   int64_t st_cap = 0;
   int32_t* order = nullptr; // device cost order of the queue
   int64_t order_cap = 0;
@@ -584,7 +615,10 @@ int launch_rhs_jac_wg(chem_mech* m, const IntArgs& a, const double* st, double* 
   return 0;
 }
 
-int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStream_t s) {
+// queue: the persistent work cursor (the mechanism's own, or the no-allocation
+// entry point's device scratch)
+int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStream_t s, int* queue = nullptr) {
+  if (!queue) queue = m->queue;
   if (m->wg) return launch_integrate_wg(m, a0, s);
   IntArgs a = a0;
   const int wpb = std::max(1, std::min(v.wpb, max_wpb(m)));
@@ -604,13 +638,13 @@ int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStrea
       occ = std::max(occ, 1);
       const int64_t need = (a.ncells + wpb - 1) / wpb;
       grid = (int)std::min<int64_t>((int64_t)m->ncu * occ * std::max(1, v.grid_mult), need);
-      a.queue = m->queue;
+      a.queue = queue;
     } else {
       a.queue = nullptr;
       grid = (int)((a.ncells + wpb - 1) / wpb);
     }
     a.failed = m->failed;
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.queue ? m->queue : nullptr, m->failed);
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.queue, m->failed);
     HIPCHK(hipGetLastError());
     if (grid > 0) {
       hipLaunchKernelGGL(kern, dim3(grid), dim3(wpb * WAVE), lds, s, a);
@@ -623,12 +657,15 @@ int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStrea
 // Builds the queue in m->order: cells with excl[i] >= 0 left out (if excl is
 // given), the rest by descending cost bucket of steps (if given); the queue
 // length goes to m->order_cnt[2 NBUCKET].
-int launch_order(chem_mech* m, const int32_t* steps, const int32_t* excl, int64_t ncells, hipStream_t s) {
+int launch_order(chem_mech* m, const int32_t* steps, const int32_t* excl, int64_t ncells, hipStream_t s,
+                 int32_t* order = nullptr, int* cnt = nullptr) {
+  if (!order) order = m->order;
+  if (!cnt) cnt = m->order_cnt;
   const int nb = (int)((ncells + 255) / 256);
-  hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(128), 0, s, m->order_cnt);
-  hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(256), 0, s, steps, excl, ncells, m->order_cnt);
-  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, m->order_cnt);
-  hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, s, steps, excl, ncells, m->order_cnt, m->order);
+  hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(128), 0, s, cnt);
+  hipLaunchKernelGGL(k_order_count, dim3(nb), dim3(256), 0, s, steps, excl, ncells, cnt);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(64), 0, s, cnt);
+  hipLaunchKernelGGL(k_order_scatter, dim3(nb), dim3(256), 0, s, steps, excl, ncells, cnt, order);
   HIPCHK(hipGetLastError());
   return 0;
 }
@@ -914,6 +951,7 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
     return fail(code, msg);
   };
   if (hipGetDevice(&m->device) != hipSuccess) return cleanup(CHEM_EHIP, "hipGetDevice failed");
+  if (noalloc_scratch(m->device, &m->noalloc_scr)) return cleanup(CHEM_EHIP, g_err);
   hipDeviceGetAttribute(&m->ncu, hipDeviceAttributeMultiprocessorCount, m->device);
   hipDeviceGetAttribute(&m->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, m->device);
   if (!wg && m->max_lds < d.lds_bytes + (int)cell_bytes(d))
@@ -1152,6 +1190,53 @@ int chem_integrate(const chem_mech* mc, int64_t ncells, int64_t ld, double* stat
     return CHEM_OK;
   }
   return launch_all(s);
+}
+
+int chem_integrate_noalloc(const chem_mech* mc, int64_t ncells, int64_t ld, double* state, double* h, double p,
+                           double dt, double rtol, double atol, const chem_options* opt, int32_t* steps,
+                           int32_t* rejects, int32_t* status, void* stream) {
+  chem_mech* m = const_cast<chem_mech*>(mc);
+  if (!m) return fail(CHEM_EINVAL, "null mechanism");
+  if (ncells < 0 || ld < ncells) return fail(CHEM_EINVAL, "need 0 <= ncells <= ld");
+  if (ncells == 0) return CHEM_OK;
+  if (!state || !h) return fail(CHEM_EINVAL, "null state or h");
+  if (!(p > 0.0) || !(dt > 0.0) || !(rtol >= 0.0) || !(atol >= 0.0) || !std::isfinite(p) || !std::isfinite(dt))
+    return fail(CHEM_EINVAL, "need p > 0, dt > 0, rtol >= 0, atol >= 0");
+  if (ncells > (int64_t)INT32_MAX) return fail(CHEM_EUNSUPPORTED, "more than 2^31-1 cells");
+  if (m->wg)
+    return fail(CHEM_EUNSUPPORTED, "the no-allocation entry point covers N <= 64 (the workgroup path needs "
+                                   "two N x N matrices of scratch per workgroup)");
+  if (opt && opt->refmap) return fail(CHEM_EUNSUPPORTED, "no reference-cell mapping in the no-allocation entry point");
+  if (opt && opt->use_graph) return fail(CHEM_EINVAL, "the no-allocation entry point keeps no graphs (capture it instead)");
+  if (!m->noalloc_scr) return fail(CHEM_EHIP, "device scratch address unavailable");
+  IntArgs a = base_args(m);
+  if (const int rc = fill_common(m, opt, a)) return rc;
+  a.state = state;
+  a.ld = ld;
+  a.ncells = ncells;
+  a.h = h;
+  a.p = 10.0 * p;
+  a.dt = dt;
+  a.rtol = rtol;
+  a.atol = atol;
+  a.steps = steps;
+  a.rejects = rejects;
+  a.status = status;
+  a.prof = opt ? (unsigned long long*)opt->phase_cycles : nullptr;
+  const Variant v = pick_variant(m, opt, ncells);
+  hipStream_t s = (hipStream_t)stream;
+  const bool ordered = opt && opt->cost_order && steps && v.persistent;
+  if (ordered && ncells > NOALLOC_MAX_ORDER)
+    return fail(CHEM_EINVAL, "cost-ordered queue of " + std::to_string(ncells) + " cells exceeds the device scratch ("
+                                 + std::to_string(NOALLOC_MAX_ORDER) + " cells)");
+  int* queue = reinterpret_cast<int*>(m->noalloc_scr);
+  if (ordered) {
+    int32_t* order = reinterpret_cast<int32_t*>(m->noalloc_scr + NOALLOC_ORDER_OFF);
+    int* cnt = reinterpret_cast<int*>(m->noalloc_scr + NOALLOC_CNT_OFF);
+    if (const int rc = launch_order(m, steps, nullptr, ncells, s, order, cnt)) return rc;
+    a.order = order;
+  }
+  return launch_integrate(m, a, v, s, queue);
 }
 
 int chem_rhs(const chem_mech* m, int64_t ncells, int64_t ld, const double* state, double p, double* f,
