@@ -27,12 +27,31 @@ FP64_PEAK_TFLOPS = 78.6
 METRIC = "cells/s integrated over one CFD dt at rtol 1e-6; adjoint gradients/s"
 
 
-def flop_model(mech: dict, method_stages: int = 4, new_f: int = 2) -> dict:
+def oracle_op_counts(name: str):
+    """F_rhs and F_jac of a workload's mechanism as counted on the oracle
+    (profiles/oracle_op_counts.md, written by oracle/op_counts_table.py), or None."""
+    import re
+    path = os.path.join(ROOT, "profiles", "oracle_op_counts.md")
+    if not os.path.exists(path):
+        return None
+    base = "c2_54sp" if name == "zonal_54sp" else name
+    got = dict(re.findall(rf"^{re.escape(base)} (f_rhs|f_jac): (\d+)", open(path).read(), flags=re.M))
+    if set(got) != {"f_rhs", "f_jac"}:
+        return None
+    return int(got["f_rhs"]), int(got["f_jac"])
+
+
+def flop_model(mech: dict, method_stages: int = 4, new_f: int = 2, name: str | None = None) -> dict:
     """Algorithmic FP64 operation counts of the method (transcendentals count 1).
 
-    F_att: one step attempt = form M + LU + s solves + new f evaluations +
-    stage combinations; F_step: the Jacobian pass (which also yields f(y_n)) of
-    each accepted step.
+    F_att: one step attempt = form M (N^2) + LU (N(N-1)/2 + (N-1)N(2N-1)/3) +
+    s solves (2N^2 - N each) + new f evaluations + stage combinations (26N);
+    F_step: the Jacobian pass (which also yields f(y_n)) of each accepted step.
+    F_rhs and the Jacobian pass are the oracle's counts for the workload's
+    mechanism (counting scalar; see oracle_op_counts); `hand` holds the
+    earlier closed-form estimates of both, which count only the operations
+    of the sparse formulation (third-body terms factored per row, constants
+    folded) and are lower.
     """
     K = int(mech["n_species"])
     R = int(mech["n_reactions"])
@@ -52,15 +71,20 @@ def flop_model(mech: dict, method_stages: int = 4, new_f: int = 2) -> dict:
             if s >= 0:
                 nu[s] = nu.get(s, 0) + 1
         L += sum(1 for v in nu.values() if v != 0)
-    f_rhs = 24 * R + 2 * tb_entries + Rtb + 37 * Rtroe + 2 * L + 41 * K + 10
+    hand_rhs = 24 * R + 2 * tb_entries + Rtb + 37 * Rtroe + 2 * L + 41 * K + 10
+    hand_jac = 45 * K + 36 * R + 60 * Rtroe + 22 * L + 16 * tb_entries + 6 * K * N
+    counted = oracle_op_counts(name) if name else None
+    f_rhs, f_jac = counted if counted else (hand_rhs, hand_jac)
     f_lu = N * (N - 1) // 2 + (N - 1) * N * (2 * N - 1) // 3
     f_solve = 2 * N * N - N
     f_att = N * N + f_lu + method_stages * f_solve + new_f * f_rhs + 26 * N
-    f_jac = 45 * K + 36 * R + 60 * Rtroe + 22 * L + 16 * tb_entries + 6 * K * N
-    return dict(f_rhs=f_rhs, f_lu=f_lu, f_solve=f_solve, f_att=f_att, f_step=f_jac, L=L)
+    hand_att = N * N + f_lu + method_stages * f_solve + new_f * hand_rhs + 26 * N
+    return dict(f_rhs=f_rhs, f_lu=f_lu, f_solve=f_solve, f_att=f_att, f_step=f_jac, L=L,
+                source="oracle op counts" if counted else "closed-form estimate",
+                hand=dict(f_rhs=hand_rhs, f_step=hand_jac, f_att=hand_att))
 
 
-def adjoint_flop_model(mech: dict, method_stages: int = 4, new_f: int = 3) -> dict:
+def adjoint_flop_model(mech: dict, method_stages: int = 4, new_f: int = 3, name: str | None = None) -> dict:
     """Algorithmic FP64 operations of one reverse step (estimates, transcendentals count 1).
 
     With checkpoints every few steps, each accepted step has to be recomputed
@@ -72,25 +96,29 @@ def adjoint_flop_model(mech: dict, method_stages: int = 4, new_f: int = 3) -> di
     one first-order product per new f evaluation (stage sources); a
     first-order product of f costs ~3 f.
     """
-    fm = flop_model(mech)
+    fm = flop_model(mech, name=name)
     f_vjp = 3 * fm["f_rhs"]
     f_rev = method_stages * (fm["f_solve"] + 3 * f_vjp) + new_f * f_vjp
     return dict(f_replay=fm["f_step"] + fm["f_att"], f_rev=f_rev, **fm)
 
 
 KERNEL_SOURCES = ("chem_common.hpp", "chem_cell.hpp", "chem_wg.hpp", "chem.hip")
+HOST_MARKER = "// ================================================================ host side"
 
 
 def kernel_source_hash(root: str = ROOT) -> str:
-    """sha256 over the integration kernel's sources with comments, trailing
-    blanks and empty lines removed: a change of code changes it, a change of
-    comments does not."""
+    """sha256 over the device code of the integration kernels (the headers and
+    the part of chem.hip before its host-side section) with comments, trailing
+    blanks and empty lines removed: a change of kernel code changes it; host
+    code and comments do not."""
     import hashlib
     import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(root, "paper_2105_12070_amd", "csrc", f)) as fh:
             txt = fh.read()
+        if f == "chem.hip":
+            txt = txt.split(HOST_MARKER)[0]
         txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
         txt = re.sub(r"//[^\n]*", "", txt)
         lines = [ln.rstrip() for ln in txt.split("\n")]
@@ -144,6 +172,8 @@ def cpu_baseline(w, mech, st0, target_s=12.0):
     return {"value": n2 / t2, "unit": "cells/s", "cores": nthreads, "kind": "oracle",
             "sample": f"first {n2} of the {st0.shape[1]} cells of {w.name}, same rtol/atol, "
                       f"OpenMP over cells, {t2:.1f} s",
+            "note": "the plain test oracle (g++ -O3 -march=x86-64-v3, no floating-point contraction, its own "
+                    "unblocked LU, no LAPACK, dense Jacobian loops), not a tuned CPU solver",
             "one_core": {"value": n1 / t3, "sample": f"first {n1} cells, {t3:.1f} s"},
             "host": {"cpus": os.cpu_count(), "model": model}}
 
@@ -151,17 +181,21 @@ def cpu_baseline(w, mech, st0, target_s=12.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2_54sp", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="c3_batch", choices=sorted(WORKLOADS),
+                    help="workload (default: the 262,144-cell batching workload, the largest that one launch "
+                         "of the driver's run covers)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--graph", action="store_true", help="launch through the cached hipGraph")
+    ap.add_argument("--graph", action="store_true", help="launch through the cached hipGraph (default for c3_batch)")
+    ap.add_argument("--no-graph", action="store_true", help="plain stream launches")
     ap.add_argument("--method", default="ros4", choices=["ros4", "rodas3", "seulex"],
                     help="integrator (ROS4 is the headline; Seulex is the paper's integrator)")
     ap.add_argument("--cost-order", action="store_true",
-                    help="persistent queue ordered by the previous call's step counts")
+                    help="persistent queue ordered by the previous call's step counts (default for c3_batch)")
+    ap.add_argument("--no-cost-order", action="store_true", help="unordered persistent queue")
     ap.add_argument("--cells", type=int, default=0, help="integrate only the first CELLS cells (profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (HBM counter calibration)")
@@ -197,6 +231,11 @@ def main():
     if args.refmap:
         return bench_refmap(args)
     w = WORKLOADS[args.config]
+    if args.config == "c3_batch":  # the batching workload is defined with the graph and the cost-ordered queue
+        args.graph = args.graph or not args.no_graph
+        args.cost_order = args.cost_order or not args.no_cost_order
+    args.graph = args.graph and not args.no_graph
+    args.cost_order = args.cost_order and not args.no_cost_order
     mech = w.mechanism()
     st0_np = w.states(mech)
     if args.cells:
@@ -248,13 +287,15 @@ def main():
     rj = rejects.cpu().numpy().astype(np.int64)
     if np.any(st != 0):
         print(f"# warning: {np.sum(st != 0)} cells with nonzero status {np.bincount(st)}", file=sys.stderr)
-    fm = flop_model(mech)
+    fm = flop_model(mech, name=w.name)
     work = None
+    flops_hand = None
     if args.method == "seulex":
         work = seulex_work(chem, m, st0, w, sp)
         flops = work.pop("flops")
     else:
         flops = float(np.sum((sp + rj) * fm["f_att"] + sp * fm["f_step"]))
+        flops_hand = float(np.sum((sp + rj) * fm["hand"]["f_att"] + sp * fm["hand"]["f_step"]))
     achieved = flops / (kern_ms * 1e-3) / 1e12
 
     plain = None
@@ -309,7 +350,9 @@ def main():
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                      "algorithmic_bytes": nc * (16 * (w.N + 1) + 12),
                      "kernel_ms": kern_ms, "kernel_ms_median": float(np.median(kern_list)),
-                     "flops_per_launch": flops},
+                     "flops_per_launch": flops, "flops_source": fm["source"],
+                     "frac_closed_form_estimate": (flops_hand / (kern_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS
+                                                   if flops_hand else None)},
         "steps_mean": float(sp.mean()), "rejects_mean": float(rj.mean()),
         "steps_percentiles_0_50_90_99_100": np.percentile(sp, [0, 50, 90, 99, 100]).tolist(),
         "plain_one_cell_per_block_cells_per_s": plain,
@@ -330,7 +373,7 @@ def seulex_work(chem, m, st0, w, steps_timed):
     extrapolation table); per attempt 10N (error norms); per step F_jac."""
     import torch
     mech = w.mechanism()
-    fm = flop_model(mech)
+    fm = flop_model(mech, name=w.name)
     N = w.N
     nc = st0.shape[1]
     s = st0.clone()
@@ -533,7 +576,7 @@ def bench_adjoint(args):
     d.record()
     torch.cuda.synchronize()
     fwd_ms, plain_ms = a.elapsed_time(b), c.elapsed_time(d)
-    fm = adjoint_flop_model(mech)
+    fm = adjoint_flop_model(mech, name=w.name)
     flops_adj = float(np.sum(sp * (fm["f_replay"] + fm["f_rev"])))
     adj_kernel_ms = max(call_ms - fwd_ms, 1e-6)
     achieved = flops_adj / (adj_kernel_ms * 1e-3) / 1e12

@@ -79,6 +79,84 @@ using std::log;
 template <class T> Dual<T> exp(const Dual<T>& a) { T e = exp(a.v); return {e, e * a.d}; }
 template <class T> Dual<T> log(const Dual<T>& a) { return {log(a.v), a.d / a.v}; }
 template <class T> Dual<T> sqrt(const Dual<T>& a) { using std::sqrt; T s = sqrt(a.v); return {s, a.d / (2.0 * s)}; }
+// ------------------------------------------------- operation-counting scalar
+// Counts the floating-point operations that f and J perform, for the
+// algorithmic FLOP figures of the roofline: additions/subtractions,
+// multiplications, divisions, exponentials and logarithms separately.  A
+// value known to be exactly zero (a zero constant or input, or a product
+// with one) makes an operation free: adding it or multiplying by it is no
+// work, so structurally zero terms of the plain dense loops are not counted.
+// One evaluation at a time (global tallies).
+struct OpTally {
+  double add = 0, mul = 0, div = 0, exp = 0, log = 0;
+};
+OpTally g_ops;
+struct Cnt {
+  double v;
+  bool zero;
+  Cnt() : v(0.0), zero(true) {}
+  Cnt(double x) : v(x), zero(x == 0.0) {}
+};
+inline double val(const Cnt& x) { return x.v; }
+inline Cnt cnt_zero() { return Cnt(); }
+inline Cnt operator+(const Cnt& a, const Cnt& b) {
+  if (a.zero) return b;
+  if (b.zero) return a;
+  g_ops.add += 1;
+  Cnt r(a.v + b.v);
+  r.zero = false;
+  return r;
+}
+inline Cnt operator-(const Cnt& a) {
+  Cnt r(-a.v);
+  r.zero = a.zero;
+  return r;
+}
+inline Cnt operator-(const Cnt& a, const Cnt& b) {
+  if (b.zero) return a;
+  if (a.zero) return -b;
+  g_ops.add += 1;
+  Cnt r(a.v - b.v);
+  r.zero = false;
+  return r;
+}
+inline Cnt operator*(const Cnt& a, const Cnt& b) {
+  if (a.zero || b.zero) return cnt_zero();
+  g_ops.mul += 1;
+  Cnt r(a.v * b.v);
+  r.zero = false;
+  return r;
+}
+inline Cnt operator/(const Cnt& a, const Cnt& b) {
+  if (a.zero) return cnt_zero();
+  g_ops.div += 1;
+  Cnt r(a.v / b.v);
+  r.zero = false;
+  return r;
+}
+inline Cnt operator+(const Cnt& a, double b) { return a + Cnt(b); }
+inline Cnt operator+(double a, const Cnt& b) { return Cnt(a) + b; }
+inline Cnt operator-(const Cnt& a, double b) { return a - Cnt(b); }
+inline Cnt operator-(double a, const Cnt& b) { return Cnt(a) - b; }
+inline Cnt operator*(const Cnt& a, double b) { return a * Cnt(b); }
+inline Cnt operator*(double a, const Cnt& b) { return Cnt(a) * b; }
+inline Cnt operator/(const Cnt& a, double b) { return a / Cnt(b); }
+inline Cnt operator/(double a, const Cnt& b) { return Cnt(a) / b; }
+inline Cnt& operator+=(Cnt& a, const Cnt& b) { a = a + b; return a; }
+inline Cnt& operator-=(Cnt& a, const Cnt& b) { a = a - b; return a; }
+inline Cnt& operator*=(Cnt& a, const Cnt& b) { a = a * b; return a; }
+inline Cnt& operator/=(Cnt& a, const Cnt& b) { a = a / b; return a; }
+inline Cnt exp(const Cnt& a) {
+  g_ops.exp += 1;
+  Cnt r(std::exp(a.v));
+  r.zero = false;
+  return r;
+}
+inline Cnt log(const Cnt& a) {
+  g_ops.log += 1;
+  return Cnt(std::log(a.v));
+}
+
 template <class S> S log10_(const S& a) { return log(a) / LN10; }
 template <class S> S pow10_(const S& a) { return exp(a * LN10); }
 template <class S> S ipow(const S& x, int n) {
@@ -998,6 +1076,32 @@ int oracle_rates(const OracleMech* m, double p_pa, const double* y, double* q, d
     if (q) q[r] = rt.q;
     if (kf_eff) kf_eff[r] = rt.keff;
     if (Kc) Kc[r] = rt.Kc;
+  }
+  return 0;
+}
+
+// Operation counts of one f evaluation (out[0..4]: add, mul, div, exp, log)
+// and of one analytic Jacobian pass, which also yields f (out[5..9]), at
+// state y, on the counting scalar (structurally zero terms are free).
+int oracle_op_counts(const OracleMech* m, double p_pa, const double* y, double* out) {
+  const int N = m->K + 1, R = m->R;
+  std::vector<Cnt> lnA(R), b(R), th(R), yc(N), f(N), J((size_t)N * N);
+  for (int r = 0; r < R; ++r) { lnA[r] = Cnt(m->lnA[r]); b[r] = Cnt(m->b[r]); th[r] = Cnt(m->theta[r]); }
+  for (int i = 0; i < N; ++i) yc[i] = Cnt(y[i]);
+  Params<Cnt> P{lnA.data(), b.data(), th.data()};
+  g_ops = OpTally{};
+  rhs(*m, P, 10.0 * p_pa, yc.data(), f.data());
+  const OpTally a = g_ops;
+  g_ops = OpTally{};
+  jac_analytic(*m, P, 10.0 * p_pa, yc.data(), J.data(), f.data());
+  const OpTally j = g_ops;
+  const OpTally* t[2] = {&a, &j};
+  for (int q = 0; q < 2; ++q) {
+    out[5 * q + 0] = t[q]->add;
+    out[5 * q + 1] = t[q]->mul;
+    out[5 * q + 2] = t[q]->div;
+    out[5 * q + 3] = t[q]->exp;
+    out[5 * q + 4] = t[q]->log;
   }
   return 0;
 }

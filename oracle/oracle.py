@@ -268,3 +268,17 @@ def controller_test(method, lam, y0, dt, rtol, atol, h=None, bound=0.0, cap=1000
                                       C.c_double(dt), C.c_double(rtol), C.c_double(atol), C.byref(o), _p(hh),
                                       _p(tr), cap, C.byref(na), C.byref(ns), C.byref(nr))
     return y, float(hh[0]), st, ns.value, nr.value, tr[:min(na.value, cap)].copy()
+
+
+OP_KINDS = ("add", "mul", "div", "exp", "log")
+
+
+def op_counts(mech, p, y):
+    """Floating-point operations of one f evaluation and of one analytic
+    Jacobian pass (which also yields f) at state y, counted on the oracle's
+    counting scalar: {"rhs": {...}, "jac": {...}} by kind."""
+    m = _as_mech(mech)
+    y = np.ascontiguousarray(y, np.float64)
+    out = np.zeros(10)
+    lib().oracle_op_counts(C.byref(m.s), C.c_double(p), _p(y), _p(out))
+    return {"rhs": dict(zip(OP_KINDS, out[:5].tolist())), "jac": dict(zip(OP_KINDS, out[5:].tolist()))}
