@@ -754,8 +754,10 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
         long long bal = 0;
         for (int s2 = 0; s2 < 3; ++s2) {
           const int a = desc->reac[3 * r + s2], b = desc->prod[3 * r + s2];
-          if (a >= 0 && a < K) bal -= desc->elem[(size_t)a * E + e];
-          if (b >= 0 && b < K) bal += desc->elem[(size_t)b * E + e];
+          if (a < -1 || a >= K || b < -1 || b >= K)
+            return fail(CHEM_EINVAL, "species index out of range in reaction " + std::to_string(r));
+          if (a >= 0) bal -= desc->elem[(size_t)a * E + e];
+          if (b >= 0) bal += desc->elem[(size_t)b * E + e];
         }
         if (bal != 0)
           return fail(CHEM_EINVAL, "reaction " + std::to_string(r) + " does not conserve element " + std::to_string(e));

@@ -603,26 +603,33 @@ __device__ inline int permute_rows(double (&row)[NP], int N, int lane, int myste
 // Solve M x = b with the permuted factors; lane i holds b_i and gets x_i.
 // The right-hand side is gathered into pivot order, then forward substitution
 // with the unit-lower L and back substitution with U (both by columns, the
-// value of step k broadcast from lane k).
+// value of step k broadcast from lane k).  Every lane applies every column's
+// update (a lane past its own step only changes a value it has already
+// saved), so no per-element triangle mask is formed: masks of the factors
+// would be loop invariants across a step's four solves and would hold two
+// masked copies of the row in registers.
 template <int NP>
 __device__ inline double lu_solve(const double (&row)[NP], int N, int lane, int src, double myrdiag, double b) {
   // padding lanes carry b = 0 and zero rows, so all NP steps run unconditionally
   (void)N;
   b = __shfl(b, src);
-  // the triangle masks act on the multipliers, which do not depend on b, so
-  // each step's dependency chain is one broadcast and one FMA (adding -0
-  // leaves b as it is)
+  double y = 0.0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     const double yk = readlane(b, k);
-    b = fma(lane > k ? -row[k] : -0.0, yk, b);
+    y = lane == k ? b : y;  // lane k's value is final at step k
+    b = fma(-row[k], yk, b);
   }
+  b = y;
+  double x = 0.0;
 #pragma unroll
   for (int k = NP - 1; k >= 0; --k) {
-    const double xk = readlane(b * myrdiag, k);
-    b = fma(lane < k ? -row[k] : -0.0, xk, b);
+    const double bk = b * myrdiag;
+    const double xk = readlane(bk, k);
+    x = lane == k ? bk : x;
+    b = fma(-row[k], xk, b);
   }
-  return b * myrdiag;
+  return x;
 }
 
 // M = I/(gamma h) - J from the LDS Jacobian into row registers.  Returns
