@@ -64,6 +64,41 @@ __global__ __launch_bounds__(max_threads<NP>()) void k_integrate(IntArgs a) {
   }
 }
 
+// The Rosenbrock integrator with Jacobian slots shared by the workgroup's
+// waves (LDS: blob, each wave's workspace without a Jacobian block, slot
+// flags, slots).  Up to eight cells per workgroup and CU instead of the four
+// whose private Jacobian blocks fit, so each SIMD runs two waves.
+template <int NP, bool PROF>
+__global__ __launch_bounds__(512) void k_integrate_pool(IntArgs a) {
+  extern __shared__ __align__(16) uint8_t lds[];
+  const int nw = blockDim.x / WAVE;
+  int* flags = (int*)(lds + a.d.lds_bytes + (size_t)nw * a.cell_doubles * sizeof(double));
+  double* slots = (double*)((uint8_t*)flags + 64);
+  if (threadIdx.x < (unsigned)a.pool_slots) flags[threadIdx.x] = 0;
+  stage_blob(lds, a.blob, a.d.lds_bytes);  // ends with a workgroup barrier
+  const MechView m = make_view(lds, a);
+  const int wv = threadIdx.x / WAVE;
+  const CellWs w = make_ws((double*)(lds + a.d.lds_bytes) + (size_t)wv * a.cell_doubles, a.d, false);
+  const SlotPool pool{flags, slots, a.pool_slots, a.d.N * a.d.S};
+  int64_t idx;
+  if (a.queue) {
+    int v = 0;
+    if (lane_id() == 0) v = atomicAdd(a.queue, 1);
+    idx = uniform_int(__shfl(v, 0));
+  } else {
+    idx = (int64_t)blockIdx.x * nw + wv;
+  }
+  const int64_t lim = a.nactive ? (int64_t)*a.nactive : a.ncells;
+  while (idx < lim) {
+    const int64_t c = a.order ? (int64_t)a.order[idx] : idx;
+    integrate_cell<NP, PROF>(m, w, a, c, &pool);
+    if (!a.queue) break;
+    int v = 0;
+    if (lane_id() == 0) v = atomicAdd(a.queue, 1);
+    idx = uniform_int(__shfl(v, 0));
+  }
+}
+
 // The same launch structure with the Seulex-family integrator.
 template <int NP, bool PROF>
 __global__ __launch_bounds__(max_threads<NP>()) void k_integrate_sx(IntArgs a) {
@@ -440,6 +475,10 @@ int fail(int code, const std::string& msg) {
 
 struct Variant {
   int persistent = 1, wpb = 4, grid_mult = 1;
+  // Jacobian slots shared by a workgroup's waves: -1 auto (the most waves that
+  // fit, when more than with private blocks), 0 none (wpb private blocks),
+  // n > 0 n slots for pool_waves waves
+  int pool = -1, pool_waves = 0;
 };
 
 // Device address of `scratch` on the current device, looked up once per
@@ -522,7 +561,7 @@ int np_for(int N) {
   return 0;
 }
 
-size_t cell_bytes(const MechDims& d) { return (size_t)cell_ws_doubles(d.N, d.S, d.R) * sizeof(double); }
+size_t cell_bytes(const MechDims& d) { return (size_t)cell_ws_doubles(d.N, d.S, d.R, d.R0) * sizeof(double); }
 
 int max_wpb(const chem_mech* m) {
   const size_t avail = (size_t)m->max_lds - m->d.lds_bytes;
@@ -535,7 +574,7 @@ IntArgs base_args(const chem_mech* m) {
   a.blob = m->blob;
   a.nasa = m->nasa;
   a.d = m->d;
-  a.cell_doubles = cell_ws_doubles(m->d.N, m->d.S, m->d.R);
+  a.cell_doubles = cell_ws_doubles(m->d.N, m->d.S, m->d.R, m->d.R0);
   return a;
 }
 
@@ -615,11 +654,76 @@ int launch_rhs_jac_wg(chem_mech* m, const IntArgs& a, const double* st, double* 
   return 0;
 }
 
+// Shared-slot layout of the Rosenbrock kernel: waves per workgroup and
+// slots.  The most waves (up to 8) for which three slots fit (two below six
+// waves); {0, 0} when no layout beats the private-Jacobian one (N <= 16, or
+// the Seulex integrator, whose steps reuse one Jacobian for many matrices).
+struct PoolLayout {
+  int waves = 0, slots = 0;
+  size_t lds = 0;
+};
+size_t pool_lds(const chem_mech* m, int waves, int slots) {
+  const MechDims& d = m->d;
+  return (size_t)d.lds_bytes + (size_t)waves * wave_rates_doubles(d.R, d.R0) * sizeof(double) + 64 +
+         (size_t)slots * d.N * d.S * sizeof(double);
+}
+PoolLayout pool_layout(const chem_mech* m, int method, int want_waves = 0, int want_slots = 0) {
+  PoolLayout L;
+  if (m->wg || method == 2 || np_for(m->d.N) <= 16) return L;
+  for (int w = 8; w > max_wpb(m); --w) {
+    if (want_waves > 0 && w != want_waves) continue;
+    const int s = want_slots > 0 ? std::min(want_slots, w) : (w >= 6 ? 3 : 2);
+    if (pool_lds(m, w, s) <= (size_t)m->max_lds) {
+      L.waves = w;
+      L.slots = s;
+      L.lds = pool_lds(m, w, s);
+      return L;
+    }
+  }
+  return L;
+}
+
+int launch_integrate_pool(chem_mech* m, const IntArgs& a0, const Variant& v, const PoolLayout& L, hipStream_t s,
+                         int* queue) {
+  IntArgs a = a0;
+  a.cell_doubles = wave_rates_doubles(m->d.R, m->d.R0);
+  a.pool_slots = L.slots;
+  return with_np(m->d.N, [&](auto npc) -> int {
+    constexpr int NP = decltype(npc)::value;
+    auto kern = (a.prof || a.jac_fd || a.lu_nopiv) ? k_integrate_pool<NP, true> : k_integrate_pool<NP, false>;
+    if (set_lds_limit<NP>((const void*)kern, L.lds)) return CHEM_EHIP;
+    int grid;
+    if (v.persistent) {
+      int occ = 0;
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, L.waves * WAVE, L.lds));
+      occ = std::max(occ, 1);
+      const int64_t need = (a.ncells + L.waves - 1) / L.waves;
+      grid = (int)std::min<int64_t>((int64_t)m->ncu * occ * std::max(1, v.grid_mult), need);
+      a.queue = queue;
+    } else {
+      a.queue = nullptr;
+      grid = (int)((a.ncells + L.waves - 1) / L.waves);
+    }
+    a.failed = m->failed;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, a.queue, m->failed);
+    HIPCHK(hipGetLastError());
+    if (grid > 0) {
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(L.waves * WAVE), L.lds, s, a);
+      HIPCHK(hipGetLastError());
+    }
+    return 0;
+  });
+}
+
 // queue: the persistent work cursor (the mechanism's own, or the no-allocation
 // entry point's device scratch)
 int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStream_t s, int* queue = nullptr) {
   if (!queue) queue = m->queue;
   if (m->wg) return launch_integrate_wg(m, a0, s);
+  if (v.pool != 0) {
+    const PoolLayout L = pool_layout(m, a0.method, v.pool_waves, v.pool > 0 ? v.pool : 0);
+    if (L.waves > 0) return launch_integrate_pool(m, a0, v, L, s, queue);
+  }
   IntArgs a = a0;
   const int wpb = std::max(1, std::min(v.wpb, max_wpb(m)));
   if (wpb < 1) return fail(CHEM_EUNSUPPORTED, "mechanism workspace does not fit in LDS");
@@ -1065,7 +1169,12 @@ static Variant pick_variant(const chem_mech* m, const chem_options* opt, int64_t
   Variant v = m->has_tuned ? m->tuned : Variant{1, max_wpb(m), 1};
   if (opt) {
     if (opt->persistent == 0 || opt->persistent == 1) v.persistent = opt->persistent;
-    if (opt->waves_per_block > 0) v.wpb = opt->waves_per_block;
+    if (opt->waves_per_block > 0) {
+      // an explicit count: private Jacobian blocks if they fit, else shared slots
+      v.wpb = opt->waves_per_block;
+      v.pool = v.wpb <= max_wpb(m) ? 0 : -1;
+      v.pool_waves = v.pool ? std::min(v.wpb, 8) : 0;
+    }
     if (opt->grid_mult > 0) v.grid_mult = opt->grid_mult;
   }
   v.wpb = std::max(1, std::min(v.wpb, max_wpb(m)));

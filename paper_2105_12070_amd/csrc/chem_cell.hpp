@@ -52,7 +52,7 @@ struct CellWs {
   double* J;    // [N][S]
   double* rk;   // [R] q (RHS) or k_eff (Jacobian)
   double* rkr;  // [R] k_eff / K_c
-  double* rdm;  // [R] d q / d[M]
+  double* rdm;  // [R - R0] d q / d[M] of the third-body and falloff reactions
   double* rdt;  // [R] d q / dT at fixed C
   double* C;    // [64+1] concentrations, C[K] = 1 (padding species)
   double* g;    // [64+1] g/RT (reused for mass enthalpy in the Jacobian pass)
@@ -60,23 +60,66 @@ struct CellWs {
   int* slot;    // [64] row permutation scratch
 };
 
+// Everything of a wave's workspace but the Jacobian block.
+__host__ __device__ inline int wave_rates_doubles(int R, int R0) { return 3 * R + (R - R0 + 1) + 3 * 66 + 32; }
 // S = NP + 1, so reads of static columns j < NP + 1 from any row stay inside
 // the J block (its last row is followed by the reaction arrays).
-__host__ __device__ inline int cell_ws_doubles(int N, int S, int R) { return N * S + 4 * R + 3 * 66 + 32; }
+__host__ __device__ inline int cell_ws_doubles(int N, int S, int R, int R0) { return N * S + wave_rates_doubles(R, R0); }
 
-__device__ inline CellWs make_ws(double* base, const MechDims& d) {
+// Workspace after base; with_J = false leaves J to be set from a slot.
+__device__ inline CellWs make_ws(double* base, const MechDims& d, bool with_J = true) {
   CellWs w;
-  w.J = base;
-  w.rk = w.J + d.N * d.S;
+  w.J = with_J ? base : nullptr;
+  w.rk = with_J ? base + d.N * d.S : base;
   w.rkr = w.rk + d.R;
-  w.rdm = w.rkr + d.R;
-  w.rdt = w.rdm + d.R;
-  w.C = w.rdt + d.R;
+  w.rdt = w.rkr + d.R;
+  w.rdm = w.rdt + d.R;
+  w.C = w.rdm + (d.R - d.R0 + 1);
   w.g = w.C + 66;
   w.hR = w.g + 66;
   w.slot = (int*)(w.hR + 66);
   return w;
 }
+
+// Jacobian slots shared by the waves of a workgroup: a wave holds one from
+// the start of the Jacobian's species pass until M is formed in registers, so
+// a workgroup can run more cells than it has Jacobian blocks.  flags[s] is 0
+// when slot s is free.  Acquisition is bounded: after `limit` sleeping polls a
+// wave gives up (the caller marks its cell failed), so no wave can wait
+// forever.
+struct SlotPool {
+  int* flags;
+  double* base;
+  int nslots;
+  int slot_doubles;
+  __device__ double* slot(int s) const { return base + (size_t)s * slot_doubles; }
+  __device__ int acquire(unsigned limit) const {
+    int got = -1;
+    for (unsigned spin = 0; spin < limit; ++spin) {
+      int v = -1;
+      if (lane_id() == 0) {
+        for (int s = 0; s < nslots; ++s) {
+          int expected = 0;
+          if (__hip_atomic_compare_exchange_strong(&flags[s], &expected, 1, __ATOMIC_ACQUIRE, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP)) {
+            v = s;
+            break;
+          }
+        }
+      }
+      got = __builtin_amdgcn_readlane(v, 0);
+      if (got >= 0) break;
+      __builtin_amdgcn_s_sleep(4);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    return got;
+  }
+  __device__ void release(int s) const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    if (lane_id() == 0) __hip_atomic_store(&flags[s], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+};
 
 // Uniform mixture quantities of one evaluation point.
 struct Mix {
@@ -339,7 +382,7 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
     }
     w.rk[r] = keff;
     w.rkr[r] = keff * iKc;
-    w.rdm[r] = dkM;
+    if (r >= m.d.R0) w.rdm[r - m.d.R0] = dkM;
     w.rdt[r] = dqdT;
   }
   if (PROF) pf->add(6, t0);
@@ -391,7 +434,7 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
         atomicAdd(Jr + 1 + s0.p2, bb * a0d0 * a0d1);
       }
       if (r0 >= m.d.R0) {
-        const double dm = nu0 * w.rdm[r0];
+        const double dm = nu0 * w.rdm[r0 - m.d.R0];
         adense += dm;
         const int t1 = m.tbp[r0 - m.d.R0 + 1];
 #pragma clang loop unroll(disable)
@@ -408,7 +451,7 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
         atomicAdd(Jr + 1 + s1.p1, bb * a1d0 * a1d2);
         atomicAdd(Jr + 1 + s1.p2, bb * a1d0 * a1d1);
         if (r1 >= m.d.R0) {
-          const double dm = nu1 * w.rdm[r1];
+          const double dm = nu1 * w.rdm[r1 - m.d.R0];
           adense += dm;
           const int t1 = m.tbp[r1 - m.d.R0 + 1];
 #pragma clang loop unroll(disable)
@@ -666,11 +709,16 @@ template <int NP, bool PROF>
 __device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosTable& tab, double p, int lane,
                                   double y, double f0, double h, double (&row)[NP], double& ynew, double& err,
                                   int& mystep, double& myrdiag, Prof<PROF>& pf, double* kst = nullptr,
-                                  int* srcout = nullptr, bool nopiv = false) {
+                                  int* srcout = nullptr, bool nopiv = false, int formed = -1) {
   const int N = m.d.N;
-  pf.start();
-  const bool okm = form_matrix<NP>(w, N, m.d.S, lane, 1.0 / (tab.gamma * h), row);
-  pf.stop(1);
+  // formed: -1 form M here from the LDS Jacobian; 1 / 0: M is already in row
+  // (formed by the caller while it held the Jacobian), finite / not finite
+  bool okm = formed == 1;
+  if (formed < 0) {
+    pf.start();
+    okm = form_matrix<NP>(w, N, m.d.S, lane, 1.0 / (tab.gamma * h), row);
+    pf.stop(1);
+  }
   if (!okm) return 2;
   const int info = lu_factor<NP>(row, N, lane, mystep, myrdiag, PROF && nopiv);
   if (info) {
@@ -725,12 +773,20 @@ __device__ inline int ros_attempt(const MechView& m, const CellWs& w, const RosT
 // follows the constants in a.ctl (accept iff err <= 1, no growth right after a
 // rejection, non-finite err rejects with fac_min, the last step is clipped to
 // dt and h_out is the last unclipped proposal capped at dt).
+//
+// With a slot pool the Jacobian block is not the wave's own: each attempt
+// takes a slot, runs the Jacobian pass (which also yields f(y)), forms M in
+// registers and gives the slot back.  A rejected attempt therefore repeats
+// the Jacobian pass; the values are the same bits as the first time, so the
+// results equal those of a wave that keeps its Jacobian.
 template <int NP, bool PROF>
-__device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs& a, int64_t c) {
+__device__ void integrate_cell(const MechView& m, const CellWs& w0, const IntArgs& a, int64_t c,
+                               const SlotPool* pool = nullptr) {
   const int lane = lane_id();
   Prof<PROF> pf;
   const unsigned long long t_begin = PROF ? __builtin_readcyclecounter() : 0ull;
   const int N = m.d.N;
+  CellWs w = w0;
   if (lane == 0) {  // padding species: C = 1, g/RT = h/RT = 0
     w.C[m.d.K] = 1.0;
     w.g[m.d.K] = 0.0;
@@ -752,10 +808,14 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
   int mystep;
   double myrdiag;
   int ntape = 0;
+  const RosTable& tab = kTables[a.method];
   while (status == ST_OK && t < dt) {
-    pf.start();
-    const double f0 = jac_pass<NP, PROF>(m, w, y, a.p, lane, row, &pf, PROF && a.jac_fd);
-    pf.stop(0);
+    double f0 = 0.0;
+    if (!pool) {
+      pf.start();
+      f0 = jac_pass<NP, PROF>(m, w, y, a.p, lane, row, &pf, PROF && a.jac_fd);
+      pf.stop(0);
+    }
     bool fresh = true;
     int nsing = 0;
     bool accepted = false;
@@ -766,11 +826,23 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w, const IntArgs
       bool clipped = false;
       if (h >= dt - t) { h = dt - t; clipped = true; }
       ++attempts;
+      int formed = -1;
+      if (pool) {
+        const int sl = pool->acquire(1u << 26);
+        if (sl < 0) { status = ST_NONFINITE; break; }  // unreachable unless a slot is never returned
+        w.J = pool->slot(sl);
+        pf.start();
+        f0 = jac_pass<NP, PROF>(m, w, y, a.p, lane, row, &pf, PROF && a.jac_fd);
+        pf.stop(0);
+        formed = form_matrix<NP>(w, N, m.d.S, lane, 1.0 / (tab.gamma * h), row) ? 1 : 0;
+        pf.stop(1);
+        pool->release(sl);
+        w.J = nullptr;
+      }
       if (fresh && ballot(lane < N && !__builtin_isfinite(f0))) { status = ST_NONFINITE; break; }
       double ynew, err;
-      const int rc =
-          ros_attempt<NP, PROF>(m, w, kTables[a.method], a.p, lane, y, f0, h, row, ynew, err, mystep, myrdiag, pf,
-                                nullptr, nullptr, PROF && a.lu_nopiv);
+      const int rc = ros_attempt<NP, PROF>(m, w, tab, a.p, lane, y, f0, h, row, ynew, err, mystep, myrdiag, pf,
+                                           nullptr, nullptr, PROF && a.lu_nopiv, formed);
       if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
       fresh = false;
       if (rc) {

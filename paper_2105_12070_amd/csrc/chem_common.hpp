@@ -86,6 +86,7 @@ struct IntArgs {
   const int32_t* order;     // optional cell order for the queue
   const int* nactive;       // optional device count of queue entries (default ncells)
   int cell_doubles;         // per-wave LDS workspace in doubles
+  int pool_slots;           // Jacobian slots shared by the workgroup's waves (0: every wave has its own)
   // adjoint tape (NULL in the forward integrator)
   double* tape_h;           // [ncells][max_tape]
   double* tape_y;           // [ncells][max_tape/ckpt + 1][N]
