@@ -1281,6 +1281,38 @@ int oracle_controller_test(int method, int n, const double* lam, double bound, d
   return r.status;
 }
 
+// The full forward-sensitivity matrix of the replayed integration: column j
+// of S ([N][N + 3R], row-major) is the derivative of the final state with
+// respect to z_j, z = (y0, lnA, b, theta), each from its own tangent-linear
+// replay (columns in parallel).  Returns the first nonzero replay code.
+int oracle_tlm_matrix(const OracleMech* m, double p_pa, int method, const double* y0, const double* hs, int n,
+                      double* S, int nthreads) {
+  const int N = m->K + 1, R = m->R, NZ = N + 3 * R;
+  int rc_all = 0;
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+  for (int j = 0; j < NZ; ++j) {
+    std::vector<double> dy0(N, 0.0), dl(R, 0.0), db(R, 0.0), dt(R, 0.0), yo(N), dyo(N);
+    if (j < N) dy0[j] = 1.0;
+    else if (j < N + R) dl[j - N] = 1.0;
+    else if (j < N + 2 * R) db[j - N - R] = 1.0;
+    else dt[j - N - 2 * R] = 1.0;
+    const int rc = oracle_tlm(m, p_pa, method, y0, hs, n, dy0.data(), dl.data(), db.data(), dt.data(), yo.data(),
+                              dyo.data());
+    if (rc) {
+#ifdef _OPENMP
+#pragma omp critical
+#endif
+      rc_all = rc;
+    }
+    for (int i = 0; i < N; ++i) S[(size_t)i * NZ + j] = dyo[i];
+  }
+  (void)nthreads;
+  return rc_all;
+}
+
 // Fixed-step integration of a built-in test problem; errout gets the embedded
 // error estimate of the last step.
 int oracle_ros_test(int method, int problem, double h, int nsteps, const double* y0, double* yout, double* errout) {

@@ -282,3 +282,17 @@ def op_counts(mech, p, y):
     out = np.zeros(10)
     lib().oracle_op_counts(C.byref(m.s), C.c_double(p), _p(y), _p(out))
     return {"rhs": dict(zip(OP_KINDS, out[:5].tolist())), "jac": dict(zip(OP_KINDS, out[5:].tolist()))}
+
+
+def tlm_matrix(mech, y0, hs, p, method="ros4", nthreads=0):
+    """Full sensitivity matrix of the replayed integration: [N, N + 3R], the
+    derivatives of the final state w.r.t. (y0, lnA, b, theta)."""
+    m = _as_mech(mech)
+    y0 = np.ascontiguousarray(y0, np.float64)
+    hs = np.ascontiguousarray(hs, np.float64)
+    S = np.zeros((m.N, m.N + 3 * m.R))
+    rc = lib().oracle_tlm_matrix(C.byref(m.s), C.c_double(p), METHOD.get(method, method), _p(y0), _p(hs),
+                                 len(hs), _p(S), C.c_int(nthreads))
+    if rc:
+        raise RuntimeError("singular matrix during tangent-linear replay")
+    return S

@@ -1,0 +1,84 @@
+#!/usr/bin/env python3
+"""Writes adjoint_fd.npz: central finite differences of the adjoint
+workload's objective with respect to the Arrhenius parameters, replaying the
+oracle's own accepted step sizes (with the controller re-run, the step
+sequence would change under the perturbation and the differences would be
+meaningless).
+
+Workload: the 53-species / 325-reaction mechanism (c4_adj) at its pressure,
+rtol 1e-6, atol 1e-10, over dt = 2e-10 s (a few hundred steps per cell: the
+initial transients of the random states are that fast), objective
+Psi = sum_cells [T + sum_k w_k Y_k](dt) with the seeded weights w.  Steps:
+1e-6 for lnA and b, 1e-6 max(|theta|, 1) for theta.
+
+  * all 975 parameters on the first 32 cells (per-cell differences stored);
+  * 20 seeded random parameters on the first 1,024 cells (per cell).
+
+The oracle's step counts per cell are stored so that the GPU test compares
+only cells whose adjoint takes the same steps.  Only the oracle is called.
+Run from the repository root:  python tests/golden/make_adjoint_fd.py
+"""
+import hashlib
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2105_12070_amd.inputs import WORKLOADS, objective_weights  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_fd.npz")
+DT = 2e-10
+
+
+def fd_column(mech, w, st, recs, weights, kind, r, cells):
+    """Central difference of each cell's objective along parameter (kind, r)."""
+    base = {k: np.array(mech[k], dtype=np.float64) for k in ("lnA", "b", "theta")}
+    key = ("lnA", "b", "theta")[kind]
+    step = 1e-6 if kind < 2 else 1e-6 * max(abs(base[key][r]), 1.0)
+    vals = []
+    for sgn in (1.0, -1.0):
+        prm = {k: v.copy() for k, v in base.items()}
+        prm[key][r] += sgn * step
+        om = oracle.Mech(mech, **prm)
+        vals.append(np.array([oracle.replay(om, st[:, c], recs[c][2], w.p_pa) @ weights for c in cells]))
+    return (vals[0] - vals[1]) / (2.0 * step)
+
+
+def main():
+    w = WORKLOADS["c4_adj"]
+    mech = w.mechanism()
+    R = mech["n_reactions"]
+    weights = np.concatenate([[1.0], objective_weights(w.n_species)])
+    st = w.states(mech, 1024)
+    om = oracle.Mech(mech)
+    t0 = time.time()
+    recs = [oracle.integrate_record(om, st[:, c], None, w.p_pa, DT, w.rtol, w.atol) for c in range(1024)]
+    assert all(r[3] == 0 for r in recs)
+    steps = np.array([len(r[2]) for r in recs], dtype=np.int32)
+    nthreads = os.cpu_count() or 8
+    with ThreadPoolExecutor(nthreads) as ex:
+        cells32 = list(range(32))
+        cols = list(ex.map(lambda q: fd_column(mech, w, st, recs, weights, q // R, q % R, cells32), range(3 * R)))
+        all32 = np.stack(cols, axis=1)  # [32 cells, 3R]
+        rng = np.random.default_rng(4005)
+        pick = np.sort(rng.choice(3 * R, 20, replace=False))
+        cells1k = list(range(1024))
+        cols = list(ex.map(lambda q: fd_column(mech, w, st, recs, weights, q // R, q % R, cells1k), pick))
+        rand1k = np.stack(cols, axis=1)  # [1024 cells, 20]
+    np.savez(OUT, steps=steps, all32=all32, pick=pick, rand1k=rand1k)
+    meta = {"dt": DT, "rtol": w.rtol, "atol": w.atol, "input_sha256": hashlib.sha256(st.tobytes()).hexdigest(),
+            "steps_min_max": [int(steps.min()), int(steps.max())], "seconds": round(time.time() - t0, 1)}
+    with open(OUT.replace(".npz", ".json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    print(json.dumps(meta))
+
+
+if __name__ == "__main__":
+    main()
