@@ -121,6 +121,11 @@ typedef struct chem_options {
   int32_t lu_pivot;   /* 0 partial pivoting [0], 1 no pivoting (rows in natural order) */
   const chem_refmap* refmap; /* NULL [NULL], or reference-cell mapping for this call
                                 (chem_integrate only; the adjoint rejects it) */
+  int32_t jac_slots;  /* N <= 64, Rosenbrock methods: 0 auto [0]; -1 every wave keeps its own
+                         Jacobian block in LDS; n > 0 the workgroup's waves share n Jacobian
+                         slots (a wave holds one from its Jacobian pass until M is formed,
+                         so more cells fit in a CU's LDS).  With N > 64, grid_mult is the
+                         number of workgroups per CU (0: as many as LDS allows). */
 } chem_options;
 
 /* Validates and uploads the mechanism; *out receives a handle to release with
@@ -244,12 +249,24 @@ int chem_lu_solve(int64_t nmat, int32_t n, const double* A, double* b, int32_t* 
 int chem_lu_factor(int64_t nmat, int32_t n, const double* A, double* LU, int32_t* ipiv, int32_t* info,
                    void* stream);
 
-/* Times the launch variants on the given input (on a scratch copy; the
- * caller's arrays are not modified) and stores the fastest as the default of
- * this mechanism.  out_variant (host int32[3], may be NULL) receives
- * {persistent, waves_per_block, grid_mult}; out_ms (host, may be NULL) its time. */
+/* The autotuner: times the launch variants on the given input (on a scratch
+ * copy; the caller's arrays are not modified) and stores the fastest as the
+ * default of this mechanism (used when an option is left at 0).  Variants:
+ * N <= 64: private Jacobian blocks (one to four cells per workgroup) or shared
+ * Jacobian slots (five to eight cells per workgroup, two to four slots, as the
+ * LDS holds them), persistent queue (grid 1 or 2 x CUs) or one launch slot per
+ * cell; N > 64: one or two workgroups per CU.  out_variant (host int32[4], may
+ * be NULL) receives {persistent, waves_per_block, grid_mult, jac_slots} as in
+ * chem_options; out_ms (host, may be NULL) the winner's time.  Every variant
+ * computes the same results bit for bit. */
 int chem_autotune(chem_mech* mech, int64_t ncells, int64_t ld, const double* state, const double* h, double p,
                   double dt, double rtol, double atol, int32_t* out_variant, double* out_ms, void* stream);
+
+/* Installs a variant as the mechanism's default (for a variant stored from an
+ * earlier chem_autotune): variant = host int32[4] {persistent, waves_per_block,
+ * grid_mult, jac_slots}.  CHEM_EINVAL if it does not fit this mechanism (too
+ * many waves or slots for the LDS, out-of-range values). */
+int chem_set_variant(chem_mech* mech, const int32_t* variant);
 
 /* Thread-local description of the last failure. */
 const char* chem_last_error(void);

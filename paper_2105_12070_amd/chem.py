@@ -52,18 +52,19 @@ class Options(C.Structure):
                 ("fac_min", C.c_double), ("fac_max", C.c_double), ("h_min", C.c_double),
                 ("persistent", C.c_int32), ("waves_per_block", C.c_int32), ("grid_mult", C.c_int32),
                 ("cost_order", C.c_int32), ("use_graph", C.c_int32), ("phase_cycles", C.c_void_p),
-                ("jac_mode", C.c_int32), ("lu_pivot", C.c_int32), ("refmap", C.POINTER(RefMap))]
+                ("jac_mode", C.c_int32), ("lu_pivot", C.c_int32), ("refmap", C.POINTER(RefMap)),
+                ("jac_slots", C.c_int32)]
 
     def __init__(self, method=0, max_steps=100000, fac_safe=0.9, fac_min=0.2, fac_max=6.0, h_min=1e-20,
                  persistent=-1, waves_per_block=0, grid_mult=0, cost_order=0, use_graph=0, phase_cycles=None,
-                 jac_mode=0, lu_pivot=0, refmap=None):
+                 jac_mode=0, lu_pivot=0, refmap=None, jac_slots=0):
         """phase_cycles: None or an int64 CUDA tensor [ncells, 8] (per-phase shader cycles);
         jac_mode 1 / lu_pivot 1 select the finite-difference Jacobian / unpivoted LU (ablation);
         refmap: None or a RefMap."""
         ptr = phase_cycles.data_ptr() if phase_cycles is not None else None
         rp = C.pointer(refmap) if refmap is not None else None
         super().__init__(method, max_steps, fac_safe, fac_min, fac_max, h_min, persistent, waves_per_block,
-                         grid_mult, cost_order, use_graph, ptr, jac_mode, lu_pivot, rp)
+                         grid_mult, cost_order, use_graph, ptr, jac_mode, lu_pivot, rp, jac_slots)
         self._keep = (phase_cycles, refmap)
 
 
@@ -96,6 +97,7 @@ def lib():
         L.chem_integrate_noalloc.argtypes = [vp, i64, i64, vp, vp, d, d, d, d, C.POINTER(Options), vp, vp, vp,
                                              vp]
         L.chem_autotune.argtypes = [vp, i64, i64, vp, vp, d, d, d, d, vp, vp, vp]
+        L.chem_set_variant.argtypes = [vp, vp]
         L.chem_set_adjoint_record_budget.argtypes = [C.c_uint64]
         _lib = L
     return _lib
@@ -323,16 +325,58 @@ def failed_count(mech: Mechanism) -> int:
     return out.value
 
 
-def autotune(mech: Mechanism, state, h, p, dt, rtol=1e-6, atol=1e-10):
-    """Times the launch variants on (a scratch copy of) the input; returns (variant, ms)."""
+VARIANT_KEYS = ("persistent", "waves_per_block", "grid_mult", "jac_slots")
+
+
+def _tune_key(mech: Mechanism, method: str) -> str:
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    return f"{arch}/N={mech.N}/R={mech.R}/{method}"
+
+
+def default_tune_cache() -> str:
+    return os.environ.get("CHEM_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_2105_12070_amd", "autotune.json"))
+
+
+def set_variant(mech: Mechanism, variant: dict) -> None:
+    """chem_set_variant: install a stored launch variant as the mechanism's default."""
+    v = (C.c_int32 * 4)(*(int(variant[k]) for k in VARIANT_KEYS))
+    _check(lib().chem_set_variant(mech.handle, C.cast(v, C.c_void_p)))
+
+
+def autotune(mech: Mechanism, state, h, p, dt, rtol=1e-6, atol=1e-10, cache: str | None = None,
+             method: str = "ros4"):
+    """Launch variant of the mechanism: from the JSON cache (keyed by GPU
+    architecture, N, R and method) when it holds one, else timed by
+    chem_autotune on (a scratch copy of) the input and stored there.  Returns
+    (variant dict, ms or None when it came from the cache).  cache=None uses
+    default_tune_cache(); cache="" disables it."""
+    import json
     _dev(state, torch.float64, "state")
     _dev(h, torch.float64, "h")
+    path = default_tune_cache() if cache is None else cache
+    key = _tune_key(mech, method)
+    table = {}
+    if path and os.path.exists(path):
+        with open(path) as f:
+            table = json.load(f)
+        if key in table:
+            set_variant(mech, table[key])
+            return dict(table[key]), None
     N, ld = state.shape
-    v = (C.c_int32 * 3)()
+    v = (C.c_int32 * 4)()
     ms = C.c_double()
     _check(lib().chem_autotune(mech.handle, ld, ld, _ptr(state), _ptr(h), float(p), float(dt), float(rtol),
                                float(atol), C.cast(v, C.c_void_p), C.cast(C.pointer(ms), C.c_void_p), _stream()))
-    return dict(persistent=v[0], waves_per_block=v[1], grid_mult=v[2]), ms.value
+    variant = dict(zip(VARIANT_KEYS, list(v)))
+    if path:
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        table[key] = variant
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    return variant, ms.value
 
 
 def set_adjoint_record_budget(nbytes: int) -> None:
@@ -344,4 +388,4 @@ def set_adjoint_record_budget(nbytes: int) -> None:
 EXPORTED = ["chem_load_mechanism", "chem_free_mechanism", "chem_max_n", "chem_mech_sizes", "chem_set_arrhenius",
             "chem_integrate", "chem_integrate_adjoint", "chem_set_adjoint_record_budget", "chem_rhs",
             "chem_jacobian", "chem_lu_solve", "chem_lu_factor", "chem_failed_count", "chem_autotune",
-            "chem_last_error", "chem_integrate_noalloc"]
+            "chem_last_error", "chem_integrate_noalloc", "chem_set_variant"]

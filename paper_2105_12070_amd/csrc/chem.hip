@@ -474,11 +474,12 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 struct Variant {
-  int persistent = 1, wpb = 4, grid_mult = 1;
+  int persistent = 1, wpb = 4, grid_mult = 1;  // grid_mult: workgroups per CU on the workgroup path
   // Jacobian slots shared by a workgroup's waves: -1 auto (the most waves that
   // fit, when more than with private blocks), 0 none (wpb private blocks),
   // n > 0 n slots for pool_waves waves
   int pool = -1, pool_waves = 0;
+  bool grid_mult_set = false;  // grid_mult given by an option or the autotuner (workgroup path)
 };
 
 // Device address of `scratch` on the current device, looked up once per
@@ -540,6 +541,8 @@ struct chem_mech {
   int32_t* adj_sptr = nullptr;
   uint32_t* adj_sent = nullptr;
   int32_t* adj_tptr = nullptr;
+  uint32_t* jsched = nullptr;  // balanced species-scatter schedule of the Jacobian (wavefront path)
+  int jsched_it = 0;
   uint32_t* adj_tent = nullptr;
   // workgroup path (64 < N <= 256): Jacobian term lists and per-workgroup scratch
   bool wg = false;
@@ -573,6 +576,8 @@ IntArgs base_args(const chem_mech* m) {
   IntArgs a{};
   a.blob = m->blob;
   a.nasa = m->nasa;
+  a.jsched = m->jsched;
+  a.jsched_it = m->jsched_it;
   a.d = m->d;
   a.cell_doubles = cell_ws_doubles(m->d.N, m->d.S, m->d.R, m->d.R0);
   return a;
@@ -608,8 +613,9 @@ WgTerms wg_terms(const chem_mech* m) {
 }
 
 // Persistent grid of the workgroup path: one workgroup per CU and LDS slot.
-int wg_grid(const chem_mech* m, int64_t items) {
-  const int per_cu = std::max(1, (int)(m->max_lds / wg_lds_bytes(m)));
+int wg_grid(const chem_mech* m, int64_t items, int per_cu_cap = 0) {
+  int per_cu = std::max(1, (int)(m->max_lds / wg_lds_bytes(m)));
+  if (per_cu_cap > 0) per_cu = std::min(per_cu, per_cu_cap);
   return (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)m->ncu * per_cu, items));
 }
 
@@ -626,9 +632,9 @@ int ensure_wg_scratch(chem_mech* m, int slots, int mats) {
   return 0;
 }
 
-int launch_integrate_wg(chem_mech* m, const IntArgs& a0, hipStream_t s) {
+int launch_integrate_wg(chem_mech* m, const IntArgs& a0, hipStream_t s, int per_cu = 0) {
   IntArgs a = a0;
-  const int grid = wg_grid(m, a.ncells);
+  const int grid = wg_grid(m, a.ncells, per_cu);
   if ((size_t)grid * 2 * m->wg_np * m->wg_np * sizeof(double) > m->wg_scr_bytes)
     return fail(CHEM_EINVAL, "workgroup scratch not prepared");
   const size_t lds = wg_lds_bytes(m);
@@ -719,7 +725,7 @@ int launch_integrate_pool(chem_mech* m, const IntArgs& a0, const Variant& v, con
 // entry point's device scratch)
 int launch_integrate(chem_mech* m, const IntArgs& a0, const Variant& v, hipStream_t s, int* queue = nullptr) {
   if (!queue) queue = m->queue;
-  if (m->wg) return launch_integrate_wg(m, a0, s);
+  if (m->wg) return launch_integrate_wg(m, a0, s, v.grid_mult_set ? v.grid_mult : 0);
   if (v.pool != 0) {
     const PoolLayout L = pool_layout(m, a0.method, v.pool_waves, v.pool > 0 ? v.pool : 0);
     if (L.waves > 0) return launch_integrate_pool(m, a0, v, L, s, queue);
@@ -913,6 +919,29 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   }
   cptr[K] = (int32_t)cent.size();
   d.L = (int)cent.size();
+  // Schedule of the Jacobian's species scatter on the wavefront path: the
+  // incidence entries dealt over species in rounds (one entry of every species
+  // that has one left per round), cut into iterations of 64 lanes; entry
+  // (r << 16) | (k << 8) | (uint8)nu, ~0u for an idle lane.  Every lane then
+  // processes about L / 64 entries instead of its own species' list.
+  std::vector<uint32_t> jsched;
+  if (!wg) {
+    if (R > 65535) return fail(CHEM_EUNSUPPORTED, "more than 65535 reactions for N <= 64");
+    std::vector<uint32_t> seq;
+    for (size_t t = 0;; ++t) {
+      bool any = false;
+      for (int k = 0; k < K; ++k) {
+        if (t >= inc[k].size()) continue;
+        const uint32_t e = inc[k][t];
+        seq.push_back(((e >> 8) << 16) | ((uint32_t)k << 8) | (e & 0xFF));
+        any = true;
+      }
+      if (!any) break;
+    }
+    const size_t nit = (seq.size() + 63) / 64;
+    jsched.assign(std::max<size_t>(nit, 1) * 64, ~0u);
+    std::copy(seq.begin(), seq.end(), jsched.begin());
+  }
   // third-body lists (non-unit efficiencies) and Troe data, internal order
   std::vector<int32_t> tbp(R - R0 + 1, 0), tbs;
   std::vector<double> tbd;
@@ -1078,6 +1107,12 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
       hipMalloc(&m->adj_sptr, 4 * sptr.size()) != hipSuccess || hipMalloc(&m->adj_sent, 4 * sent.size()) != hipSuccess ||
       hipMalloc(&m->adj_tptr, 4 * tptr.size()) != hipSuccess || hipMalloc(&m->adj_tent, 4 * tent.size()) != hipSuccess)
     return cleanup(CHEM_ENOMEM, "device allocation failed");
+  if (!jsched.empty()) {
+    m->jsched_it = (int)(jsched.size() / 64);
+    if (hipMalloc(&m->jsched, 4 * jsched.size()) != hipSuccess) return cleanup(CHEM_ENOMEM, "device allocation failed");
+    if (hipMemcpy(m->jsched, jsched.data(), 4 * jsched.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(CHEM_EHIP, "upload failed");
+  }
   if (hipMemcpy(m->adj_sptr, sptr.data(), 4 * sptr.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->adj_sent, sent.data(), 4 * sent.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(m->adj_tptr, tptr.data(), 4 * tptr.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1117,6 +1152,7 @@ void chem_free_mechanism(chem_mech* m) {
   hipFree(m->adj_sent);
   hipFree(m->adj_tptr);
   hipFree(m->adj_tent);
+  hipFree(m->jsched);
   delete m;
 }
 
@@ -1166,16 +1202,28 @@ static int fill_common(const chem_mech* m, const chem_options* opt, IntArgs& a) 
 }
 
 static Variant pick_variant(const chem_mech* m, const chem_options* opt, int64_t ncells) {
-  Variant v = m->has_tuned ? m->tuned : Variant{1, max_wpb(m), 1};
+  Variant v = m->has_tuned ? m->tuned : Variant{};
+  if (!m->has_tuned) v.wpb = max_wpb(m);
   if (opt) {
     if (opt->persistent == 0 || opt->persistent == 1) v.persistent = opt->persistent;
-    if (opt->waves_per_block > 0) {
-      // an explicit count: private Jacobian blocks if they fit, else shared slots
-      v.wpb = opt->waves_per_block;
-      v.pool = v.wpb <= max_wpb(m) ? 0 : -1;
-      v.pool_waves = v.pool ? std::min(v.wpb, 8) : 0;
+    if (opt->grid_mult > 0) {
+      v.grid_mult = opt->grid_mult;
+      v.grid_mult_set = true;
     }
-    if (opt->grid_mult > 0) v.grid_mult = opt->grid_mult;
+    if (opt->jac_slots == -1) {
+      v.pool = 0;
+    } else if (opt->jac_slots > 0) {
+      v.pool = opt->jac_slots;
+      v.pool_waves = opt->waves_per_block;  // 0: the most that fit
+    }
+    if (opt->waves_per_block > 0) {
+      v.wpb = opt->waves_per_block;
+      if (opt->jac_slots == 0) {
+        // a count alone: private Jacobian blocks if they fit, else shared slots
+        v.pool = v.wpb <= max_wpb(m) ? 0 : -1;
+        v.pool_waves = v.pool ? std::min(v.wpb, 8) : 0;
+      }
+    }
   }
   v.wpb = std::max(1, std::min(v.wpb, max_wpb(m)));
   (void)ncells;
@@ -1458,19 +1506,58 @@ int chem_failed_count(const chem_mech* m, int64_t* out, void* stream) {
   return CHEM_OK;
 }
 
+// Variant <-> the option fields that select it.
+static void variant_options(const Variant& v, chem_options& o) {
+  o.persistent = v.persistent;
+  o.waves_per_block = v.pool > 0 ? v.pool_waves : v.wpb;
+  o.grid_mult = v.grid_mult;
+  o.jac_slots = v.pool > 0 ? v.pool : -1;
+}
+static void variant_out(const chem_mech* m, const Variant& v, int32_t* out) {
+  out[0] = v.persistent;
+  out[1] = m->wg ? 4 : (v.pool > 0 ? v.pool_waves : v.wpb);
+  out[2] = v.grid_mult;
+  out[3] = m->wg ? 0 : (v.pool > 0 ? v.pool : -1);
+}
+
+// The candidate launch variants of a mechanism (every one computes the same bits).
+static std::vector<Variant> tune_candidates(const chem_mech* m) {
+  std::vector<Variant> c;
+  auto add = [&](int persistent, int wpb, int gm, int pool, int pool_waves) {
+    Variant v;
+    v.persistent = persistent;
+    v.wpb = wpb;
+    v.grid_mult = gm;
+    v.grid_mult_set = true;
+    v.pool = pool;
+    v.pool_waves = pool_waves;
+    c.push_back(v);
+  };
+  if (m->wg) {
+    const int per_cu = std::max(1, (int)(m->max_lds / wg_lds_bytes(m)));
+    for (int g = 1; g <= per_cu; ++g) add(1, 4, g, 0, 0);
+    return c;
+  }
+  for (int w = 1; w <= max_wpb(m); ++w) {  // private Jacobian blocks
+    add(0, w, 1, 0, 0);
+    add(1, w, 1, 0, 0);
+    add(1, w, 2, 0, 0);
+  }
+  if (np_for(m->d.N) > 16) {  // shared Jacobian slots
+    for (int w = max_wpb(m) + 1; w <= 8; ++w)
+      for (int sl = 2; sl <= std::min(4, w); ++sl) {
+        if (pool_lds(m, w, sl) > (size_t)m->max_lds) continue;
+        add(1, w, 1, sl, w);
+        add(1, w, 2, sl, w);
+      }
+  }
+  return c;
+}
+
 int chem_autotune(chem_mech* m, int64_t ncells, int64_t ld, const double* state, const double* h, double p,
                   double dt, double rtol, double atol, int32_t* out_variant, double* out_ms, void* stream) {
   if (!m || !state || !h) return fail(CHEM_EINVAL, "null argument");
   if (ncells < 1 || ld < ncells) return fail(CHEM_EINVAL, "need 1 <= ncells <= ld");
-  if (m->wg) {  // the workgroup path has a single launch shape
-    if (out_variant) {
-      out_variant[0] = 1;
-      out_variant[1] = 1;
-      out_variant[2] = 1;
-    }
-    if (out_ms) *out_ms = 0.0;
-    return CHEM_OK;
-  }
   const int N = m->d.N;
   hipStream_t s = (hipStream_t)stream;
   double *st = nullptr, *hh = nullptr;
@@ -1481,12 +1568,7 @@ int chem_autotune(chem_mech* m, int64_t ncells, int64_t ld, const double* state,
   hipEvent_t e0, e1;
   hipEventCreate(&e0);
   hipEventCreate(&e1);
-  std::vector<Variant> cands;
-  for (int w = 1; w <= max_wpb(m); ++w) {
-    cands.push_back({0, w, 1});
-    cands.push_back({1, w, 1});
-    cands.push_back({1, w, 2});
-  }
+  const std::vector<Variant> cands = tune_candidates(m);
   Variant best = cands.front();
   double best_ms = 1e300;
   int rc = 0;
@@ -1498,9 +1580,7 @@ int chem_autotune(chem_mech* m, int64_t ncells, int64_t ld, const double* state,
   o.fac_max = 6.0;
   o.h_min = 1e-20;
   for (const Variant& v : cands) {
-    o.persistent = v.persistent;
-    o.waves_per_block = v.wpb;
-    o.grid_mult = v.grid_mult;
+    variant_options(v, o);
     double ms_best = 1e300;
     for (int rep = 0; rep < 2 && rc == 0; ++rep) {
       hipMemcpy2DAsync(st, sizeof(double) * ncells, state, sizeof(double) * ld, sizeof(double) * ncells, N,
@@ -1527,12 +1607,35 @@ int chem_autotune(chem_mech* m, int64_t ncells, int64_t ld, const double* state,
   if (rc) return rc;
   m->tuned = best;
   m->has_tuned = true;
-  if (out_variant) {
-    out_variant[0] = best.persistent;
-    out_variant[1] = best.wpb;
-    out_variant[2] = best.grid_mult;
-  }
+  if (out_variant) variant_out(m, best, out_variant);
   if (out_ms) *out_ms = best_ms;
+  return CHEM_OK;
+}
+
+int chem_set_variant(chem_mech* m, const int32_t* v) {
+  if (!m || !v) return fail(CHEM_EINVAL, "null argument");
+  if ((v[0] != 0 && v[0] != 1) || v[2] < 1 || v[2] > 64) return fail(CHEM_EINVAL, "invalid variant");
+  Variant x;
+  x.persistent = v[0];
+  x.grid_mult = v[2];
+  x.grid_mult_set = true;
+  if (m->wg) {
+    const int per_cu = std::max(1, (int)(m->max_lds / wg_lds_bytes(m)));
+    if (v[2] > per_cu) return fail(CHEM_EINVAL, "more workgroups per CU than the LDS holds");
+    x.persistent = 1;
+  } else if (v[3] > 0) {
+    if (np_for(m->d.N) <= 16 || v[1] < 1 || v[1] > 8 || v[3] > v[1] || pool_lds(m, v[1], v[3]) > (size_t)m->max_lds)
+      return fail(CHEM_EINVAL, "shared-slot variant does not fit this mechanism");
+    x.pool = v[3];
+    x.pool_waves = v[1];
+    x.wpb = max_wpb(m);
+  } else {
+    if (v[3] != -1 || v[1] < 1 || v[1] > max_wpb(m)) return fail(CHEM_EINVAL, "private-block variant does not fit");
+    x.pool = 0;
+    x.wpb = v[1];
+  }
+  m->tuned = x;
+  m->has_tuned = true;
   return CHEM_OK;
 }
 

@@ -26,6 +26,8 @@ struct MechView {
   const double* tbd;      // LDS efficiency - 1
   const double* troe;     // LDS [R - R1][8]
   const double* nasa;     // global [K][16]
+  const uint32_t* jsched; // global [jit][64] species-scatter schedule: (r << 16) | (k << 8) | (uint8)nu
+  int jit;
 };
 
 __device__ inline MechView make_view(const uint8_t* lds, const IntArgs& a) {
@@ -44,6 +46,8 @@ __device__ inline MechView make_view(const uint8_t* lds, const IntArgs& a) {
   m.tbd = (const double*)(lds + a.d.o_tbd);
   m.troe = (const double*)(lds + a.d.o_troe);
   m.nasa = a.nasa;
+  m.jsched = a.jsched;
+  m.jit = a.jsched_it;
   return m;
 }
 
@@ -387,80 +391,62 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
   }
   if (PROF) pf->add(6, t0);
   const unsigned long long t1 = PROF ? pf->now() : 0ull;
-  // species rows of dw/dC (sparse, lane-owned rows of J)
+  // species rows of dw/dC (sparse), scattered by the balanced schedule: lane l
+  // takes entry it * 64 + l, species k and reaction r, and adds to row k of J.
+  // While they are built, omega_k, d omega_k / dT and the row's dense
+  // third-body sum are accumulated in J[k+1][0] (column 0, written after this
+  // pass), hR[k] (free after the reaction phase) and J[0][k+1] (row 0, written
+  // after this pass).  All additions are LDS atomics, in schedule order and,
+  // within one instruction, in the hardware's lane order: deterministic.
   const bool isSp = lane >= 1 && lane <= K;
   double* Jr = w.J + lane * S;  // S = NP + 1: every static column index stays in the row
   if (lane < N) {
 #pragma unroll
     for (int j = 0; j < NP + 1; ++j) Jr[j] = 0.0;
   }
+  if (isSp) w.hR[lane - 1] = 0.0;
   wsync();
-  double om = 0.0, dwdT = 0.0, adense = 0.0;
-  if (isSp) {
-    const int k = lane - 1;
-    const int e1 = m.cptr[k + 1];
-    int e = m.cptr[k];
-    // entries two at a time (the second masked off past the end, so the
-    // iteration has no branch on it); the next pair's table words are loaded
-    // one iteration ahead.  Sums and LDS adds keep the entries' order.
-    uint32_t va = e < e1 ? m.cent[e] : 0u, vb = e + 1 < e1 ? m.cent[e + 1] : 0u;
-    uint64_t sa = e < e1 ? m.sp[va >> 8] : 0ull, sb = e < e1 ? m.sp[vb >> 8] : 0ull;
+  {
+    const uint32_t* js = m.jsched + lane;
+    uint32_t ent = js[0];
 #pragma clang loop unroll(disable)
-    for (; e < e1; e += 2) {
-      const bool hb = e + 1 < e1;
-      const uint32_t v0 = va, v1 = vb;
-      const Slots s0 = unpack(sa), s1 = unpack(sb);
-      va = e + 2 < e1 ? m.cent[e + 2] : 0u;
-      vb = e + 3 < e1 ? m.cent[e + 3] : 0u;
-      const int r0 = (int)(v0 >> 8), r1 = (int)(v1 >> 8);
-      const double nu0 = (double)(int8_t)(v0 & 0xFF), nu1 = hb ? (double)(int8_t)(v1 & 0xFF) : 0.0;
-      const double a0c0 = w.C[s0.r0], a0c1 = w.C[s0.r1], a0c2 = w.C[s0.r2];
-      const double a0d0 = w.C[s0.p0], a0d1 = w.C[s0.p1], a0d2 = w.C[s0.p2];
-      const double a1c0 = w.C[s1.r0], a1c1 = w.C[s1.r1], a1c2 = w.C[s1.r2];
-      const double a1d0 = w.C[s1.p0], a1d1 = w.C[s1.p1], a1d2 = w.C[s1.p2];
-      const double kf0 = w.rk[r0], kr0 = w.rkr[r0], dt0 = w.rdt[r0];
-      const double kf1 = w.rk[r1], kr1 = w.rkr[r1], dt1 = w.rdt[r1];
-      sa = m.sp[va >> 8];
-      sb = m.sp[vb >> 8];
-      om += nu0 * (kf0 * a0c0 * a0c1 * a0c2 - kr0 * a0d0 * a0d1 * a0d2);
-      dwdT += nu0 * dt0;
-      {
-        const double a = nu0 * kf0, bb = -nu0 * kr0;
-        atomicAdd(Jr + 1 + s0.r0, a * a0c1 * a0c2);
-        atomicAdd(Jr + 1 + s0.r1, a * a0c0 * a0c2);
-        atomicAdd(Jr + 1 + s0.r2, a * a0c0 * a0c1);
-        atomicAdd(Jr + 1 + s0.p0, bb * a0d1 * a0d2);
-        atomicAdd(Jr + 1 + s0.p1, bb * a0d0 * a0d2);
-        atomicAdd(Jr + 1 + s0.p2, bb * a0d0 * a0d1);
-      }
-      if (r0 >= m.d.R0) {
-        const double dm = nu0 * w.rdm[r0 - m.d.R0];
-        adense += dm;
-        const int t1 = m.tbp[r0 - m.d.R0 + 1];
+    for (int it = 0; it < m.jit; ++it) {
+      const uint32_t cur = ent;
+      if (it + 1 < m.jit) ent = js[(it + 1) * WAVE];
+      if (cur != ~0u) {
+        const int r = (int)(cur >> 16), k = (int)((cur >> 8) & 0xFF);
+        const double nu = (double)(int8_t)(cur & 0xFF);
+        const Slots sl = unpack(m.sp[r]);
+        const double c0 = w.C[sl.r0], c1 = w.C[sl.r1], c2 = w.C[sl.r2];
+        const double d0 = w.C[sl.p0], d1 = w.C[sl.p1], d2 = w.C[sl.p2];
+        const double kf = w.rk[r], kr = w.rkr[r], dq = w.rdt[r];
+        double* Jk = w.J + (k + 1) * S;
+        atomicAdd(Jk, nu * (kf * c0 * c1 * c2 - kr * d0 * d1 * d2));
+        atomicAdd(w.hR + k, nu * dq);
+        const double a = nu * kf, bb = -nu * kr;
+        atomicAdd(Jk + 1 + sl.r0, a * c1 * c2);
+        atomicAdd(Jk + 1 + sl.r1, a * c0 * c2);
+        atomicAdd(Jk + 1 + sl.r2, a * c0 * c1);
+        atomicAdd(Jk + 1 + sl.p0, bb * d1 * d2);
+        atomicAdd(Jk + 1 + sl.p1, bb * d0 * d2);
+        atomicAdd(Jk + 1 + sl.p2, bb * d0 * d1);
+        if (r >= m.d.R0) {
+          const double dm = nu * w.rdm[r - m.d.R0];
+          atomicAdd(w.J + 1 + k, dm);
+          const int t1 = m.tbp[r - m.d.R0 + 1];
 #pragma clang loop unroll(disable)
-        for (int q = m.tbp[r0 - m.d.R0]; q < t1; ++q) atomicAdd(Jr + 1 + m.tbs[q], dm * m.tbd[q]);
-      }
-      if (hb) {
-        om += nu1 * (kf1 * a1c0 * a1c1 * a1c2 - kr1 * a1d0 * a1d1 * a1d2);
-        dwdT += nu1 * dt1;
-        const double a = nu1 * kf1, bb = -nu1 * kr1;
-        atomicAdd(Jr + 1 + s1.r0, a * a1c1 * a1c2);
-        atomicAdd(Jr + 1 + s1.r1, a * a1c0 * a1c2);
-        atomicAdd(Jr + 1 + s1.r2, a * a1c0 * a1c1);
-        atomicAdd(Jr + 1 + s1.p0, bb * a1d1 * a1d2);
-        atomicAdd(Jr + 1 + s1.p1, bb * a1d0 * a1d2);
-        atomicAdd(Jr + 1 + s1.p2, bb * a1d0 * a1d1);
-        if (r1 >= m.d.R0) {
-          const double dm = nu1 * w.rdm[r1 - m.d.R0];
-          adense += dm;
-          const int t1 = m.tbp[r1 - m.d.R0 + 1];
-#pragma clang loop unroll(disable)
-          for (int q = m.tbp[r1 - m.d.R0]; q < t1; ++q) atomicAdd(Jr + 1 + m.tbs[q], dm * m.tbd[q]);
+          for (int q = m.tbp[r - m.d.R0]; q < t1; ++q) atomicAdd(Jk + 1 + m.tbs[q], dm * m.tbd[q]);
         }
       }
     }
   }
   wsync();
+  double om = 0.0, dwdT = 0.0, adense = 0.0;
+  if (isSp) {
+    om = Jr[0];
+    dwdT = w.hR[lane - 1];
+    adense = w.J[lane];
+  }
   // dense transform of the lane's row: rank-1 density term and W scaling
   // (uniform loop bounds: no per-column branches; padding columns set to 0)
   double fk = 0.0;

@@ -70,6 +70,8 @@ struct Controller {
 struct IntArgs {
   const uint8_t* blob;      // LDS-staged part of the mechanism (global copy)
   const double* nasa;       // [K][16] Tmid, lo a1..a7, hi a1..a7, pad
+  const uint32_t* jsched;   // [jsched_it][64] species-scatter schedule of the Jacobian (wavefront path)
+  int jsched_it;
   MechDims d;
   int method;               // index into kTables
   double q;                 // controller exponent 1/q (4 ROS4, 3 Rodas3)
