@@ -12,7 +12,13 @@ Psi = sum_cells [T + sum_k w_k Y_k](dt) with the seeded weights w.  Steps:
 1e-6 for lnA and b, 1e-6 max(|theta|, 1) for theta.
 
   * all 975 parameters on the first 32 cells (per-cell differences stored);
-  * 20 seeded random parameters on the first 1,024 cells (per cell).
+  * 20 seeded random parameters on the first 1,024 cells (per cell), as
+    central differences and as the oracle's tangent-linear derivative of the
+    same replay.  Summed over 1,024 cells the differences carry the rounding
+    noise of every cell's replay (about 1e-14 of Psi per cell over a few
+    hundred steps, divided by the 1e-6 step): about 1e-4 absolute, above the
+    bound for the smallest entries, so that check uses the tangent-linear
+    values, which are exact derivatives of the replayed map.
 
 The oracle's step counts per cell are stored so that the GPU test compares
 only cells whose adjoint takes the same steps.  Only the oracle is called.
@@ -51,6 +57,16 @@ def fd_column(mech, w, st, recs, weights, kind, r, cells):
     return (vals[0] - vals[1]) / (2.0 * step)
 
 
+def tlm_column(mech, w, st, recs, weights, kind, r, cells):
+    """Each cell's d Psi_c / d p along parameter (kind, r) by the tangent-linear replay."""
+    R = mech["n_reactions"]
+    d = [np.zeros(R), np.zeros(R), np.zeros(R)]
+    d[kind][r] = 1.0
+    om = oracle.Mech(mech)
+    return np.array([oracle.tlm(om, st[:, c], recs[c][2], w.p_pa, dlnA=d[0], db=d[1], dtheta=d[2])[1] @ weights
+                     for c in cells])
+
+
 def main():
     w = WORKLOADS["c4_adj"]
     mech = w.mechanism()
@@ -72,7 +88,9 @@ def main():
         cells1k = list(range(1024))
         cols = list(ex.map(lambda q: fd_column(mech, w, st, recs, weights, q // R, q % R, cells1k), pick))
         rand1k = np.stack(cols, axis=1)  # [1024 cells, 20]
-    np.savez(OUT, steps=steps, all32=all32, pick=pick, rand1k=rand1k)
+        cols = list(ex.map(lambda q: tlm_column(mech, w, st, recs, weights, q // R, q % R, cells1k), pick))
+        tlm1k = np.stack(cols, axis=1)  # [1024 cells, 20]
+    np.savez(OUT, steps=steps, all32=all32, pick=pick, rand1k=rand1k, tlm1k=tlm1k)
     meta = {"dt": DT, "rtol": w.rtol, "atol": w.atol, "input_sha256": hashlib.sha256(st.tobytes()).hexdigest(),
             "steps_min_max": [int(steps.min()), int(steps.max())], "seconds": round(time.time() - t0, 1)}
     with open(OUT.replace(".npz", ".json"), "w") as f:
