@@ -21,97 +21,147 @@
 
 namespace chem {
 
-// ---------------------------------------------------------------- dual numbers
-struct Dd {
-  double v, d;
+// ------------------------------------------------- tangents and their adjoints
+// The second-order terms sum_i (J'(y_n)[K_i])^T u_i are taken two stages at a
+// time by reverse mode over a two-direction forward mode: forward values F2
+// carry the value and its derivatives along K_a and K_b; adjoint values A3
+// carry the adjoint of the value (p, which collects the second-order terms),
+// the adjoints of the two derivatives (t0, t1, seeded with u_a and u_b: these
+// are first-order adjoints for those seeds) and one more first-order adjoint
+// (w, seeded with another weight on f).  For z = x * y with x, y forward
+// values: xbar.t_j += zbar.t_j y.v, xbar.w += zbar.w y.v and
+// xbar.p += zbar.p y.v + sum_j zbar.t_j y.d_j.  At the end p holds
+// sum_j (J'[K_j])^T u_j and w holds J^T w_seed; the t parts are not needed.
+struct F2 {
+  double v, d0, d1;
 };
-__device__ __forceinline__ Dd mk(double v, double d = 0.0) { return Dd{v, d}; }
-__device__ __forceinline__ Dd operator+(Dd a, Dd b) { return {a.v + b.v, a.d + b.d}; }
-__device__ __forceinline__ Dd operator-(Dd a, Dd b) { return {a.v - b.v, a.d - b.d}; }
-__device__ __forceinline__ Dd operator*(Dd a, Dd b) { return {a.v * b.v, fma(a.d, b.v, a.v * b.d)}; }
-__device__ __forceinline__ Dd operator/(Dd a, Dd b) {
-  const double q = a.v / b.v;
-  return {q, (a.d - q * b.d) / b.v};
+__device__ __forceinline__ F2 operator+(F2 a, F2 b) { return {a.v + b.v, a.d0 + b.d0, a.d1 + b.d1}; }
+__device__ __forceinline__ F2 operator-(F2 a, F2 b) { return {a.v - b.v, a.d0 - b.d0, a.d1 - b.d1}; }
+__device__ __forceinline__ F2 operator*(F2 a, F2 b) {
+  return {a.v * b.v, fma(a.d0, b.v, a.v * b.d0), fma(a.d1, b.v, a.v * b.d1)};
 }
-__device__ __forceinline__ Dd operator-(Dd a) { return {-a.v, -a.d}; }
-__device__ __forceinline__ Dd operator+(Dd a, double b) { return {a.v + b, a.d}; }
-__device__ __forceinline__ Dd operator+(double a, Dd b) { return {a + b.v, b.d}; }
-__device__ __forceinline__ Dd operator-(Dd a, double b) { return {a.v - b, a.d}; }
-__device__ __forceinline__ Dd operator-(double a, Dd b) { return {a - b.v, -b.d}; }
-__device__ __forceinline__ Dd operator*(Dd a, double b) { return {a.v * b, a.d * b}; }
-__device__ __forceinline__ Dd operator*(double a, Dd b) { return {a * b.v, a * b.d}; }
-__device__ __forceinline__ Dd operator/(Dd a, double b) { return {a.v / b, a.d / b}; }
-__device__ __forceinline__ Dd operator/(double a, Dd b) {
-  const double q = a / b.v;
-  return {q, -q * b.d / b.v};
+__device__ __forceinline__ F2 operator/(F2 a, F2 b) {
+  const double q = a.v / b.v, ib = 1.0 / b.v;
+  return {q, (a.d0 - q * b.d0) * ib, (a.d1 - q * b.d1) * ib};
 }
-__device__ __forceinline__ Dd& operator+=(Dd& a, Dd b) { return a = a + b; }
-__device__ __forceinline__ Dd& operator-=(Dd& a, Dd b) { return a = a - b; }
+__device__ __forceinline__ F2 operator-(F2 a) { return {-a.v, -a.d0, -a.d1}; }
+__device__ __forceinline__ F2 operator+(F2 a, double b) { return {a.v + b, a.d0, a.d1}; }
+__device__ __forceinline__ F2 operator+(double a, F2 b) { return {a + b.v, b.d0, b.d1}; }
+__device__ __forceinline__ F2 operator-(F2 a, double b) { return {a.v - b, a.d0, a.d1}; }
+__device__ __forceinline__ F2 operator-(double a, F2 b) { return {a - b.v, -b.d0, -b.d1}; }
+__device__ __forceinline__ F2 operator*(F2 a, double b) { return {a.v * b, a.d0 * b, a.d1 * b}; }
+__device__ __forceinline__ F2 operator*(double a, F2 b) { return {a * b.v, a * b.d0, a * b.d1}; }
+__device__ __forceinline__ F2 operator/(F2 a, double b) { return {a.v / b, a.d0 / b, a.d1 / b}; }
+__device__ __forceinline__ F2 operator/(double a, F2 b) {
+  const double q = a / b.v, s = -q / b.v;
+  return {q, s * b.d0, s * b.d1};
+}
+__device__ __forceinline__ F2& operator+=(F2& a, F2 b) { return a = a + b; }
+__device__ __forceinline__ F2& operator-=(F2& a, F2 b) { return a = a - b; }
+
+struct A3 {
+  double p, t0, t1, w;
+};
+__device__ __forceinline__ A3 operator+(A3 a, A3 b) { return {a.p + b.p, a.t0 + b.t0, a.t1 + b.t1, a.w + b.w}; }
+__device__ __forceinline__ A3 operator-(A3 a, A3 b) { return {a.p - b.p, a.t0 - b.t0, a.t1 - b.t1, a.w - b.w}; }
+__device__ __forceinline__ A3 operator-(A3 a) { return {-a.p, -a.t0, -a.t1, -a.w}; }
+__device__ __forceinline__ A3 operator*(A3 a, double b) { return {a.p * b, a.t0 * b, a.t1 * b, a.w * b}; }
+__device__ __forceinline__ A3 operator*(double a, A3 b) { return b * a; }
+__device__ __forceinline__ A3 operator/(A3 a, double b) { return {a.p / b, a.t0 / b, a.t1 / b, a.w / b}; }
+__device__ __forceinline__ A3 operator*(A3 a, F2 x) {
+  return {fma(a.t1, x.d1, fma(a.t0, x.d0, a.p * x.v)), a.t0 * x.v, a.t1 * x.v, a.w * x.v};
+}
+__device__ __forceinline__ A3 operator*(F2 x, A3 a) { return a * x; }
+__device__ __forceinline__ A3 operator/(A3 a, F2 x) { return a * (1.0 / x); }
+__device__ __forceinline__ A3& operator+=(A3& a, A3 b) { return a = a + b; }
+__device__ __forceinline__ A3& operator-=(A3& a, A3 b) { return a = a - b; }
 
 __device__ __forceinline__ double sexp(double x) { return exp(x); }
-__device__ __forceinline__ Dd sexp(Dd x) {
+__device__ __forceinline__ F2 sexp(F2 x) {
   const double e = exp(x.v);
-  return {e, e * x.d};
+  return {e, e * x.d0, e * x.d1};
 }
 __device__ __forceinline__ double slog(double x) { return log(x); }
-__device__ __forceinline__ Dd slog(Dd x) { return {log(x.v), x.d / x.v}; }
+__device__ __forceinline__ F2 slog(F2 x) {
+  const double i = 1.0 / x.v;
+  return {log(x.v), x.d0 * i, x.d1 * i};
+}
 __device__ __forceinline__ double slog10(double x) { return log10(x); }
-__device__ __forceinline__ Dd slog10(Dd x) { return {log10(x.v), x.d / (x.v * 2.302585092994045684)}; }
+__device__ __forceinline__ F2 slog10(F2 x) {
+  const double i = 1.0 / (x.v * 2.302585092994045684);
+  return {log10(x.v), x.d0 * i, x.d1 * i};
+}
 __device__ __forceinline__ double sexp10(double x) { return exp10(x); }
-__device__ __forceinline__ Dd sexp10(Dd x) {
-  const double e = exp10(x.v);
-  return {e, e * 2.302585092994045684 * x.d};
+__device__ __forceinline__ F2 sexp10(F2 x) {
+  const double e = exp10(x.v), s = e * 2.302585092994045684;
+  return {e, s * x.d0, s * x.d1};
 }
 __device__ __forceinline__ double rl(double x, int l) { return readlane(x, l); }
-__device__ __forceinline__ Dd rl(Dd x, int l) { return {readlane(x.v, l), readlane(x.d, l)}; }
+__device__ __forceinline__ F2 rl(F2 x, int l) { return {readlane(x.v, l), readlane(x.d0, l), readlane(x.d1, l)}; }
+__device__ __forceinline__ A3 rl(A3 x, int l) {
+  return {readlane(x.p, l), readlane(x.t0, l), readlane(x.t1, l), readlane(x.w, l)};
+}
 __device__ __forceinline__ double wsum(double x) { return wave_sum(x); }
-__device__ __forceinline__ Dd wsum(Dd x) { return {wave_sum(x.v), wave_sum(x.d)}; }
-// the part of a value that a pass contributes: the value itself in the
-// first-order pass, the derivative part in the dual (second-order) pass
+__device__ __forceinline__ F2 wsum(F2 x) { return {wave_sum(x.v), wave_sum(x.d0), wave_sum(x.d1)}; }
+__device__ __forceinline__ A3 wsum(A3 x) { return {wave_sum(x.p), wave_sum(x.t0), wave_sum(x.t1), wave_sum(x.w)}; }
 __device__ __forceinline__ double sval(double x) { return x; }
-__device__ __forceinline__ double sval(Dd x) { return x.v; }
+__device__ __forceinline__ double sval(F2 x) { return x.v; }
+// what a pass contributes to lambda_n and to the parameter gradient: the
+// adjoint itself in the first-order pass; the second-order terms plus the
+// extra first-order adjoint in the combined pass
 __device__ __forceinline__ double part(double x) { return x; }
-__device__ __forceinline__ double part(Dd x) { return x.d; }
+__device__ __forceinline__ double part(A3 x) { return x.p + x.w; }
 template <class S>
 __device__ __forceinline__ S zero();
 template <>
 __device__ __forceinline__ double zero<double>() { return 0.0; }
 template <>
-__device__ __forceinline__ Dd zero<Dd>() { return Dd{0.0, 0.0}; }
+__device__ __forceinline__ F2 zero<F2>() { return F2{0.0, 0.0, 0.0}; }
+template <>
+__device__ __forceinline__ A3 zero<A3>() { return A3{0.0, 0.0, 0.0, 0.0}; }
 template <class S>
 __device__ __forceinline__ S one();
 template <>
 __device__ __forceinline__ double one<double>() { return 1.0; }
 template <>
-__device__ __forceinline__ Dd one<Dd>() { return Dd{1.0, 0.0}; }
+__device__ __forceinline__ F2 one<F2>() { return F2{1.0, 0.0, 0.0}; }
 
-// Adjoint workspace in LDS (arrays of S; the double pass uses the same bytes).
+// Adjoint workspace in LDS: forward values F, adjoint values A.  The rates of
+// progress of the forward part (q) and the adjoints of R_f (aR) share bytes.
 // The adjoint of sum nu g/RT of reaction r is aP[r] R_r, recomputed where it
 // is needed, so it takes no array.
-template <class S>
+template <class F, class A>
 struct AdjView {
-  S* C;   // [66] concentrations (padding species 1)
-  S* g;   // [66] g/RT
-  S* hR;  // [66] h/RT
-  S* ob;  // [66] adjoint of omega (padding 0)
-  S* aR;  // [R] q in the forward part, then adjoint of R_f
-  S* aP;  // [R] adjoint of R_r
-  S* Mb;  // [R - R0] adjoint of [M] of the third-body and Troe reactions
+  F* C;   // [66] concentrations (padding species 1)
+  F* g;   // [66] g/RT
+  F* hR;  // [66] h/RT
+  A* ob;  // [66] adjoint of omega (padding 0)
+  F* q;   // [R] rates of progress (forward part)
+  A* aR;  // [R] adjoint of R_f (reverse part; same bytes as q)
+  A* aP;  // [R] adjoint of R_r
+  A* Mb;  // [R - R0] adjoint of [M] of the third-body and Troe reactions
 };
 
-// Doubles of the workspace: room for the dual-number (two-double) pass.
-__host__ __device__ inline int adj_ws_doubles(int R, int R0) { return 2 * (4 * 66 + 2 * R + (R - R0)); }
+template <class F, class A>
+__host__ __device__ inline int adj_doubles(int R, int R0) {
+  constexpr int f = (int)(sizeof(F) / sizeof(double)), a = (int)(sizeof(A) / sizeof(double));
+  constexpr int qa = f > a ? f : a;
+  return 198 * f + 66 * a + R * qa + R * a + (R - R0) * a;
+}
 
-template <class S>
-__device__ inline AdjView<S> make_adj(double* base, int R) {
-  AdjView<S> v;
-  S* b = (S*)base;
-  v.C = b;
-  v.g = b + 66;
-  v.hR = b + 132;
-  v.ob = b + 198;
-  v.aR = b + 264;
-  v.aP = v.aR + R;
+template <class F, class A>
+__device__ inline AdjView<F, A> make_adj(double* base, int R) {
+  constexpr int f = (int)(sizeof(F) / sizeof(double)), a = (int)(sizeof(A) / sizeof(double));
+  constexpr int qa = f > a ? f : a;
+  AdjView<F, A> v;
+  v.C = (F*)base;
+  v.g = v.C + 66;
+  v.hR = v.g + 66;
+  v.ob = (A*)(base + 198 * f);
+  double* qb = base + 198 * f + 66 * a;
+  v.q = (F*)qb;
+  v.aR = (A*)qb;
+  v.aP = (A*)(qb + (size_t)R * qa);
   v.Mb = v.aP + R;
   return v;
 }
@@ -131,8 +181,8 @@ struct RateLoc {
 };
 
 // Rate of progress of reaction r with the local derivatives the reverse pass needs.
-template <class S>
-__device__ inline RateLoc<S> rate_loc(const MechView& m, const AdjView<S>& v, int r, S T, S lnT, S iT, S Ctot,
+template <class S, class A>
+__device__ inline RateLoc<S> rate_loc(const MechView& m, const AdjView<S, A>& v, int r, S T, S lnT, S iT, S Ctot,
                                       S lnPRT) {
   const Slots s = unpack(m.sp[r]);
   RateLoc<S> o;
@@ -186,40 +236,42 @@ __device__ inline RateLoc<S> rate_loc(const MechView& m, const AdjView<S>& v, in
 }
 
 // u^T f(y) differentiated in reverse mode: returns (J(y)^T u)_lane and adds
-// part((df/dp)^T u) to pg[3r + {0,1,2}] = d/dlnA, d/db, d/dtheta.  u is the
-// lane-local weight on f_lane; y may be dual (then the returned derivative part
-// is (J'[dy])^T u and pg receives the derivative parts).
-template <class S>
-__device__ S vjp_f(const MechView& m, const AdjMech& am, const AdjView<S>& v, double* pg, S y, double u, double p,
+// part((df/dp)^T u) to pg[3r + {0,1,2}] = d/dlnA, d/db, d/dtheta (the cell's
+// gradient accumulators, lane-owned entries).  u is the lane-local weight on
+// f_lane.  With F = F2 and A = A3 (y carries the directions K_a, K_b; u the
+// seeds u_a, u_b and w) the returned p part is sum_j (J'[K_j])^T u_j, the w
+// part J^T w, and pg receives both parameter parts.
+template <class F, class A>
+__device__ A vjp_f(const MechView& m, const AdjMech& am, const AdjView<F, A>& v, double* pg, F y, A u, double p,
                    int lane) {
   const int K = m.d.K, R = m.d.R;
   const bool isSp = lane >= 1 && lane <= K;
   const int k = isSp ? lane - 1 : 0;
   if (lane == 0) {  // padding species
-    v.C[K] = one<S>();
-    v.g[K] = zero<S>();
-    v.hR[K] = zero<S>();
-    v.ob[K] = zero<S>();
+    v.C[K] = one<F>();
+    v.g[K] = zero<F>();
+    v.hR[K] = zero<F>();
+    v.ob[K] = zero<A>();
   }
   // ---- forward part
-  const S T = rl(y, 0);
-  const S lnT = slog(T);
-  const S iT = 1.0 / T;
+  const F T = rl(y, 0);
+  const F lnT = slog(T);
+  const F iT = 1.0 / T;
   const double* row = m.nasa + 16 * k;
   const double* a = (sval(T) > row[0]) ? row + 8 : row + 1;
-  const S cpR = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
-  const S hRT = a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + T * a[4] * 0.2))) + a[5] * iT;
-  const S sR = a[0] * lnT + T * (a[1] + T * (a[2] * 0.5 + T * (a[3] * (1.0 / 3.0) + T * a[4] * 0.25))) + a[6];
-  const S dcpR = a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + T * 4.0 * a[4]));
+  const F cpR = a[0] + T * (a[1] + T * (a[2] + T * (a[3] + T * a[4])));
+  const F hRT = a[0] + T * (a[1] * 0.5 + T * (a[2] * (1.0 / 3.0) + T * (a[3] * 0.25 + T * a[4] * 0.2))) + a[5] * iT;
+  const F sR = a[0] * lnT + T * (a[1] + T * (a[2] * 0.5 + T * (a[3] * (1.0 / 3.0) + T * a[4] * 0.25))) + a[6];
+  const F dcpR = a[1] + T * (2.0 * a[2] + T * (3.0 * a[3] + T * 4.0 * a[4]));
   const double Wk = m.W[k], iWk = m.iW[k];
-  const S Yk = isSp ? y : zero<S>();
-  const S yw = Yk * iWk;
-  const S sy = wsum(yw);
-  const S rho = p / (RU * T * sy);
-  const S Ctot = p * iT / RU;
-  const S lnPRT = slog(PATM * iT / RU);
-  const S cpm = isSp ? RU * cpR * iWk : zero<S>();
-  const S cp = wsum(Yk * cpm);
+  const F Yk = isSp ? y : zero<F>();
+  const F yw = Yk * iWk;
+  const F sy = wsum(yw);
+  const F rho = p / (RU * T * sy);
+  const F Ctot = p * iT / RU;
+  const F lnPRT = slog(PATM * iT / RU);
+  const F cpm = isSp ? RU * cpR * iWk : zero<F>();
+  const F cp = wsum(Yk * cpm);
   if (isSp) {
     v.C[k] = rho * yw;
     v.g[k] = hRT - sR;
@@ -227,39 +279,41 @@ __device__ S vjp_f(const MechView& m, const AdjMech& am, const AdjView<S>& v, do
   }
   wsync();
   for (int r = lane; r < R; r += WAVE) {
-    const RateLoc<S> o = rate_loc<S>(m, v, r, T, lnT, iT, Ctot, lnPRT);
-    v.aR[r] = o.keff * o.net;
+    const RateLoc<F> o = rate_loc<F, A>(m, v, r, T, lnT, iT, Ctot, lnPRT);
+    v.q[r] = o.keff * o.net;
   }
   wsync();
-  S om = zero<S>();
+  F om = zero<F>();
   if (isSp) {
     for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
       const uint32_t cv = m.cent[e];
-      om += (double)(int8_t)(cv & 0xFF) * v.aR[cv >> 8];
+      om += (double)(int8_t)(cv & 0xFF) * v.q[cv >> 8];
     }
   }
-  const S Q = wsum(isSp ? hRT * om : zero<S>());
-  const S fT = -RU * T * Q / (rho * cp);
-  const S fk = isSp ? Wk * om / rho : zero<S>();
+  const F Q = wsum(isSp ? hRT * om : zero<F>());
+  const F fT = -RU * T * Q / (rho * cp);
+  const F fk = isSp ? Wk * om / rho : zero<F>();
   // ---- reverse part
-  const double uT = readlane(u, 0);
-  const S Qb = -uT * RU * T / (rho * cp);
-  const S rhob1 = wsum(isSp ? -u * fk / rho : zero<S>()) - uT * fT / rho;
-  const S cpb = -uT * fT / cp;
-  S Tb = uT * fT * iT;
-  S hRTb = isSp ? Qb * om : zero<S>();
+  const A uT = rl(u, 0);
+  const A Qb = -uT * RU * T / (rho * cp);
+  const A rhob1 = wsum(isSp ? -u * fk / rho : zero<A>()) - uT * fT / rho;
+  const A cpb = -uT * fT / cp;
+  A Tb = uT * fT * iT;
+  A hRTb = isSp ? Qb * om : zero<A>();
   if (isSp) v.ob[k] = u * Wk / rho + Qb * hRT;
   wsync();
-  S Tbr = zero<S>();
+  A Tbr = zero<A>();
   for (int r = lane; r < R; r += WAVE) {
-    const RateLoc<S> o = rate_loc<S>(m, v, r, T, lnT, iT, Ctot, lnPRT);
+    double* pgr = pg + 3 * r;
+    const double g0 = pgr[0], g1 = pgr[1], g2 = pgr[2];
+    const RateLoc<F> o = rate_loc<F, A>(m, v, r, T, lnT, iT, Ctot, lnPRT);
     const Slots s = unpack(m.sp[r]);
-    const S qb = v.ob[s.p0] + v.ob[s.p1] + v.ob[s.p2] - v.ob[s.r0] - v.ob[s.r1] - v.ob[s.r2];
-    const S keffb = qb * o.net;
-    const S netb = qb * o.keff;
-    const S sngb = -netb * o.Rr * o.iKc;
+    const A qb = v.ob[s.p0] + v.ob[s.p1] + v.ob[s.p2] - v.ob[s.r0] - v.ob[s.r1] - v.ob[s.r2];
+    const A keffb = qb * o.net;
+    const A netb = qb * o.keff;
+    const A sngb = -netb * o.Rr * o.iKc;
     Tbr += (double)s.dnu * sngb * iT;
-    S lnkb, Mb = zero<S>();
+    A lnkb, Mb = zero<A>();
     if (r < m.d.R1) {
       lnkb = keffb * o.keff;
       Tbr += lnkb * o.dlnkf;
@@ -273,19 +327,19 @@ __device__ S vjp_f(const MechView& m, const AdjMech& am, const AdjView<S>& v, do
     v.aR[r] = netb;
     v.aP[r] = -netb * o.iKc;
     if (r >= m.d.R0) v.Mb[r - m.d.R0] = Mb;
-    pg[3 * r + 0] += part(lnkb);
-    pg[3 * r + 1] += part(lnkb * lnT);
-    pg[3 * r + 2] -= part(lnkb * iT);
+    pgr[0] = g0 + part(lnkb);
+    pgr[1] = g1 + part(lnkb * lnT);
+    pgr[2] = g2 - part(lnkb * iT);
   }
   wsync();
-  S Cb = zero<S>(), gb = zero<S>();
+  A Cb = zero<A>(), gb = zero<A>();
   if (isSp) {
     for (int e = am.sptr[k]; e < am.sptr[k + 1]; ++e) {
       const uint32_t ev = am.sent[e];
       const int r = (int)(ev >> 3), slot = (int)(ev & 7);
       const Slots s = unpack(m.sp[r]);
-      const S aP = v.aP[r];
-      const S sn = aP * (v.C[s.p0] * v.C[s.p1] * v.C[s.p2]);  // adjoint of sum nu g/RT
+      const A aP = v.aP[r];
+      const A sn = aP * (v.C[s.p0] * v.C[s.p1] * v.C[s.p2]);  // adjoint of sum nu g/RT
       if (slot < 3) {
         const int o1 = slot == 0 ? s.r1 : s.r0, o2 = slot == 2 ? s.r1 : s.r2;
         Cb += v.aR[r] * (v.C[o1] * v.C[o2]);
@@ -302,33 +356,39 @@ __device__ S vjp_f(const MechView& m, const AdjMech& am, const AdjView<S>& v, do
     }
   }
   hRTb += gb;
-  const S sRb = -gb;
-  const S cpRb = isSp ? cpb * Yk * RU * iWk : zero<S>();
-  const S Tth = isSp ? hRTb * (cpR - hRT) * iT + sRb * cpR * iT + cpRb * dcpR : zero<S>();
-  S Yb = isSp ? cpb * cpm : zero<S>();
-  const S rhob = rhob1 + wsum(isSp ? Cb * yw : zero<S>());
-  S ywb = isSp ? Cb * rho : zero<S>();
+  const A sRb = -gb;
+  const A cpRb = isSp ? cpb * Yk * RU * iWk : zero<A>();
+  const A Tth = isSp ? hRTb * (cpR - hRT) * iT + sRb * cpR * iT + cpRb * dcpR : zero<A>();
+  A Yb = isSp ? cpb * cpm : zero<A>();
+  const A rhob = rhob1 + wsum(isSp ? Cb * yw : zero<A>());
+  A ywb = isSp ? Cb * rho : zero<A>();
   Tb += wsum(Tbr) + wsum(Tth) - rhob * rho * iT;
-  const S syb = -rhob * rho / sy;
+  const A syb = -rhob * rho / sy;
   ywb += syb;
   Yb += ywb * iWk;
   wsync();
-  return lane == 0 ? Tb : (isSp ? Yb : zero<S>());
+  return lane == 0 ? Tb : (isSp ? Yb : zero<A>());
 }
 
-// Solve M^T x = b with the pivot-ordered factors stored row-wise in LDS F
-// (row k of P M = L U on lane k): U^T z = b, L^T v = z, x = P^T v.
+// Solve M^T x = b with the pivot-ordered factors P M = L U stored row-wise in
+// LDS F (row k of P M = L U at F + k S): U^T z = b, L^T v = z, x = P^T v.
+// Lane j first loads column j of the factors into registers (all loads in
+// flight together), so the two triangular sweeps run on registers and
+// readlane broadcasts only.  Rows >= N are not factors: those steps are
+// skipped (uniform branch); padding lanes read column 0 and are masked.  The
+// masks act on the multipliers, off the chain through b (adding -0 leaves b
+// as it is).
 template <int NP>
 __device__ inline double lu_solve_T(const double* F, int N, int S, int lane, int mystep, double myrdiag, double b) {
-  // rows >= N of F are not factors: those steps are skipped (uniform branch);
-  // padding lanes read column 0 and are masked.  The masks act on the
-  // multipliers, off the chain through b (adding -0 leaves b as it is).
   const int col = lane < N ? lane : 0;
+  double cv[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) cv[k] = k < N ? F[k * S + col] : 0.0;
 #pragma unroll
   for (int k = 0; k < NP; ++k) {
     if (k < N) {
       const double zk = readlane(b * myrdiag, k);
-      b = fma((lane > k && lane < N) ? -F[k * S + col] : -0.0, zk, b);
+      b = fma((lane > k && lane < N) ? -cv[k] : -0.0, zk, b);
     }
   }
   b *= myrdiag;
@@ -336,7 +396,7 @@ __device__ inline double lu_solve_T(const double* F, int N, int S, int lane, int
   for (int k = NP - 1; k >= 0; --k) {
     if (k < N) {
       const double vk = readlane(b, k);
-      b = fma(lane < k ? -F[k * S + col] : -0.0, vk, b);
+      b = fma(lane < k ? -cv[k] : -0.0, vk, b);
     }
   }
   return __shfl(b, mystep);
