@@ -148,14 +148,15 @@ def cpu_baseline(w, mech, st0, target_s=12.0):
     import oracle
     oracle.build(force=False)
     nthreads = oracle.num_threads()
-    n = 32
-    t0 = time.perf_counter()
-    oracle.integrate(mech, st0[:, :n], None, w.p_pa, w.dt, w.rtol, w.atol, nthreads=nthreads)
-    t1 = time.perf_counter() - t0
-    n2 = int(min(max(n, n * (target_s - t1) / max(t1, 1e-3)), 65536, st0.shape[1]))
-    t0 = time.perf_counter()
-    oracle.integrate(mech, st0[:, :n2], None, w.p_pa, w.dt, w.rtol, w.atol, nthreads=nthreads)
-    t2 = time.perf_counter() - t0
+    # grow the sample (first n cells) until one run takes at least target_s
+    n2, t2 = 32, 0.0
+    while True:
+        t0 = time.perf_counter()
+        oracle.integrate(mech, st0[:, :n2], None, w.p_pa, w.dt, w.rtol, w.atol, nthreads=nthreads)
+        t2 = time.perf_counter() - t0
+        if t2 >= target_s or n2 >= min(65536, st0.shape[1]):
+            break
+        n2 = int(min(n2 * min(max(1.2 * target_s / max(t2, 1e-3), 2.0), 64.0), 65536, st0.shape[1]))
     # one core, on a smaller sample
     n1 = max(4, min(n2, int(n2 / max(nthreads, 1) / 2)))
     t0 = time.perf_counter()
@@ -183,9 +184,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c3_batch", choices=sorted(WORKLOADS),
-                    help="workload (default: the 262,144-cell batching workload, the largest that one launch "
-                         "of the driver's run covers)")
+    ap.add_argument("--config", default=None, choices=sorted(WORKLOADS),
+                    help="workload (default: the 262,144-cell batching workload; with --adjoint the "
+                         "16,384-cell adjoint workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -197,6 +198,8 @@ def main():
                     help="persistent queue ordered by the previous call's step counts (default for c3_batch)")
     ap.add_argument("--no-cost-order", action="store_true", help="unordered persistent queue")
     ap.add_argument("--cells", type=int, default=0, help="integrate only the first CELLS cells (profiling)")
+    ap.add_argument("--progress", action="store_true",
+                    help="synchronise after every launch and report it on stderr (long launches under a profiler)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--ablation", action="store_true",
@@ -208,8 +211,8 @@ def main():
                     help="zonal workload with and without reference-cell mapping of the ambient zone")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: the cells are independent, and the multi-GPU "
-              "sharding is described in DESIGN.md but not part of this build", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the cells are independent, and sharding them over "
+              "several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -230,6 +233,7 @@ def main():
         return bench_adjoint(args)
     if args.refmap:
         return bench_refmap(args)
+    args.config = args.config or "c3_batch"
     w = WORKLOADS[args.config]
     if args.config == "c3_batch":  # the batching workload is defined with the graph and the cost-ordered queue
         args.graph = args.graph or not args.no_graph
@@ -252,7 +256,7 @@ def main():
 
     variant = None
     if not args.no_autotune:
-        sub = min(nc, 8192)
+        sub = min(nc, 65536)  # enough cells that throughput, not the slowest cell, decides
         variant, _ = chem.autotune(m, st0[:, :sub].contiguous(), torch.zeros(sub, dtype=torch.float64, device=dev),
                                    w.p_pa, w.dt, w.rtol, w.atol)
         print(f"# autotune on {sub} cells: {variant}", file=sys.stderr, flush=True)
@@ -271,13 +275,21 @@ def main():
         if ev:
             ev[1].record()
 
-    for _ in range(args.warmup):
+    def progress(msg):
+        if args.progress:
+            torch.cuda.synchronize()
+            print(f"# {msg} done ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
+    t_start = time.perf_counter()
+    for i in range(args.warmup):
         one_step()
+        progress(f"warmup {i}")
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t0 = time.perf_counter()
     for i in range(args.steps):
         one_step(evs[i])
+        progress(f"step {i}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kern_list = [a.elapsed_time(b) for a, b in evs]
@@ -310,6 +322,7 @@ def main():
         b.record()
         torch.cuda.synchronize()
         plain = nc / (a.elapsed_time(b) * 1e-3)
+        progress("plain launch")
 
     # a warm call: the same cells again from the step sizes the last call
     # returned (the flow solver calls the chemistry again within a time step)
@@ -323,6 +336,7 @@ def main():
                    status=status)
     wb.record()
     torch.cuda.synchronize()
+    progress("warm call")
     warm = {"cells_per_s": nc / (wa.elapsed_time(wb) * 1e-3),
             "steps_mean": float(steps.float().mean()), "rejects_mean": float(rejects.float().mean())}
 
@@ -519,7 +533,7 @@ def bench_adjoint(args):
     from paper_2105_12070_amd import chem
     from paper_2105_12070_amd.inputs import objective_weights
 
-    name = args.config if args.config != "c2_54sp" else "c4_adj"
+    name = args.config or "c4_adj"
     w = WORKLOADS[name]
     mech = w.mechanism()
     st0_np = w.states(mech)
