@@ -126,6 +126,12 @@ typedef struct chem_options {
                          slots (a wave holds one from its Jacobian pass until M is formed,
                          so more cells fit in a CU's LDS).  With N > 64, grid_mult is the
                          number of workgroups per CU (0: as many as LDS allows). */
+  int64_t fail_lu_lo, fail_lu_hi; /* testing [0, 0]: cells with index in [fail_lu_lo, fail_lu_hi)
+                         see every factorisation of M as singular (a zero pivot), so the
+                         controller's singular branch runs: the step is halved and retried,
+                         and the sixth consecutive singular attempt of a step ends the cell
+                         with CHEM_CELL_SINGULAR, its state at the step start and h_out the last
+                         attempted step size.  CHEM_EINVAL unless 0 <= lo <= hi. */
 } chem_options;
 
 /* Validates and uploads the mechanism; *out receives a handle to release with

@@ -53,18 +53,20 @@ class Options(C.Structure):
                 ("persistent", C.c_int32), ("waves_per_block", C.c_int32), ("grid_mult", C.c_int32),
                 ("cost_order", C.c_int32), ("use_graph", C.c_int32), ("phase_cycles", C.c_void_p),
                 ("jac_mode", C.c_int32), ("lu_pivot", C.c_int32), ("refmap", C.POINTER(RefMap)),
-                ("jac_slots", C.c_int32)]
+                ("jac_slots", C.c_int32), ("fail_lu_lo", C.c_int64), ("fail_lu_hi", C.c_int64)]
 
     def __init__(self, method=0, max_steps=100000, fac_safe=0.9, fac_min=0.2, fac_max=6.0, h_min=1e-20,
                  persistent=-1, waves_per_block=0, grid_mult=0, cost_order=0, use_graph=0, phase_cycles=None,
-                 jac_mode=0, lu_pivot=0, refmap=None, jac_slots=0):
+                 jac_mode=0, lu_pivot=0, refmap=None, jac_slots=0, fail_lu=(0, 0)):
         """phase_cycles: None or an int64 CUDA tensor [ncells, 8] (per-phase shader cycles);
         jac_mode 1 / lu_pivot 1 select the finite-difference Jacobian / unpivoted LU (ablation);
-        refmap: None or a RefMap."""
+        refmap: None or a RefMap; fail_lu = (lo, hi): testing, cells lo..hi-1 see every
+        factorisation as singular."""
         ptr = phase_cycles.data_ptr() if phase_cycles is not None else None
         rp = C.pointer(refmap) if refmap is not None else None
         super().__init__(method, max_steps, fac_safe, fac_min, fac_max, h_min, persistent, waves_per_block,
-                         grid_mult, cost_order, use_graph, ptr, jac_mode, lu_pivot, rp, jac_slots)
+                         grid_mult, cost_order, use_graph, ptr, jac_mode, lu_pivot, rp, jac_slots,
+                         int(fail_lu[0]), int(fail_lu[1]))
         self._keep = (phase_cycles, refmap)
 
 

@@ -1198,6 +1198,9 @@ static int fill_common(const chem_mech* m, const chem_options* opt, IntArgs& a) 
   if ((o.jac_mode || o.lu_pivot) && m->wg) return fail(CHEM_EUNSUPPORTED, "ablation switches need N <= 64");
   a.jac_fd = o.jac_mode;
   a.lu_nopiv = o.lu_pivot;
+  if (o.fail_lu_lo < 0 || o.fail_lu_hi < o.fail_lu_lo) return fail(CHEM_EINVAL, "need 0 <= fail_lu_lo <= fail_lu_hi");
+  a.fail_lu_lo = o.fail_lu_lo;
+  a.fail_lu_hi = o.fail_lu_hi;
   return 0;
 }
 

@@ -32,7 +32,9 @@ namespace chem {
 // values: xbar.t_j += zbar.t_j y.v, xbar.w += zbar.w y.v and
 // xbar.p += zbar.p y.v + sum_j zbar.t_j y.d_j.  At the end p holds
 // sum_j (J'[K_j])^T u_j and w holds J^T w_seed; the t parts are not needed.
-struct F2 {
+// Both types view LDS bytes that the other type also uses (the forward rates
+// and the reverse adjoints share an array), so they may alias anything.
+struct __attribute__((may_alias)) F2 {
   double v, d0, d1;
 };
 __device__ __forceinline__ F2 operator+(F2 a, F2 b) { return {a.v + b.v, a.d0 + b.d0, a.d1 + b.d1}; }
@@ -59,7 +61,7 @@ __device__ __forceinline__ F2 operator/(double a, F2 b) {
 __device__ __forceinline__ F2& operator+=(F2& a, F2 b) { return a = a + b; }
 __device__ __forceinline__ F2& operator-=(F2& a, F2 b) { return a = a - b; }
 
-struct A3 {
+struct __attribute__((may_alias)) A3 {
   double p, t0, t1, w;
 };
 __device__ __forceinline__ A3 operator+(A3 a, A3 b) { return {a.p + b.p, a.t0 + b.t0, a.t1 + b.t1, a.w + b.w}; }
@@ -75,6 +77,21 @@ __device__ __forceinline__ A3 operator*(F2 x, A3 a) { return a * x; }
 __device__ __forceinline__ A3 operator/(A3 a, F2 x) { return a * (1.0 / x); }
 __device__ __forceinline__ A3& operator+=(A3& a, A3 b) { return a = a + b; }
 __device__ __forceinline__ A3& operator-=(A3& a, A3 b) { return a = a - b; }
+
+// LDS accumulation, component by component (within one instruction the
+// hardware applies conflicting lanes in a fixed order)
+__device__ __forceinline__ void atomic_add(double* p, double v) { atomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(F2* p, F2 v) {
+  atomicAdd(&p->v, v.v);
+  atomicAdd(&p->d0, v.d0);
+  atomicAdd(&p->d1, v.d1);
+}
+__device__ __forceinline__ void atomic_add(A3* p, A3 v) {
+  atomicAdd(&p->p, v.p);
+  atomicAdd(&p->t0, v.t0);
+  atomicAdd(&p->t1, v.t1);
+  atomicAdd(&p->w, v.w);
+}
 
 __device__ __forceinline__ double sexp(double x) { return exp(x); }
 __device__ __forceinline__ F2 sexp(F2 x) {
@@ -134,19 +151,19 @@ template <class F, class A>
 struct AdjView {
   F* C;   // [66] concentrations (padding species 1)
   F* g;   // [66] g/RT
-  F* hR;  // [66] h/RT
+  F* om;  // [66] production rates omega (accumulated)
   A* ob;  // [66] adjoint of omega (padding 0)
   F* q;   // [R] rates of progress (forward part)
   A* aR;  // [R] adjoint of R_f (reverse part; same bytes as q)
   A* aP;  // [R] adjoint of R_r
-  A* Mb;  // [R - R0] adjoint of [M] of the third-body and Troe reactions
+  A* Mb;  // [R - R0 + 1] adjoint of [M] of the third-body and Troe reactions
 };
 
 template <class F, class A>
 __host__ __device__ inline int adj_doubles(int R, int R0) {
   constexpr int f = (int)(sizeof(F) / sizeof(double)), a = (int)(sizeof(A) / sizeof(double));
   constexpr int qa = f > a ? f : a;
-  return 198 * f + 66 * a + R * qa + R * a + (R - R0) * a;
+  return 198 * f + 66 * a + R * qa + R * a + (R - R0 + 1) * a;
 }
 
 template <class F, class A>
@@ -156,7 +173,7 @@ __device__ inline AdjView<F, A> make_adj(double* base, int R) {
   AdjView<F, A> v;
   v.C = (F*)base;
   v.g = v.C + 66;
-  v.hR = v.g + 66;
+  v.om = v.g + 66;
   v.ob = (A*)(base + 198 * f);
   double* qb = base + 198 * f + 66 * a;
   v.q = (F*)qb;
@@ -250,9 +267,8 @@ __device__ A vjp_f(const MechView& m, const AdjMech& am, const AdjView<F, A>& v,
   if (lane == 0) {  // padding species
     v.C[K] = one<F>();
     v.g[K] = zero<F>();
-    v.hR[K] = zero<F>();
-    v.ob[K] = zero<A>();
   }
+  for (int i = lane; i < 66; i += WAVE) v.om[i] = zero<F>();
   // ---- forward part
   const F T = rl(y, 0);
   const F lnT = slog(T);
@@ -275,7 +291,6 @@ __device__ A vjp_f(const MechView& m, const AdjMech& am, const AdjView<F, A>& v,
   if (isSp) {
     v.C[k] = rho * yw;
     v.g[k] = hRT - sR;
-    v.hR[k] = hRT;
   }
   wsync();
   for (int r = lane; r < R; r += WAVE) {
@@ -283,13 +298,19 @@ __device__ A vjp_f(const MechView& m, const AdjMech& am, const AdjView<F, A>& v,
     v.q[r] = o.keff * o.net;
   }
   wsync();
-  F om = zero<F>();
-  if (isSp) {
-    for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
-      const uint32_t cv = m.cent[e];
-      om += (double)(int8_t)(cv & 0xFF) * v.q[cv >> 8];
+  // omega_k = sum_r nu_kr q_r on the balanced species schedule
+  {
+    const uint32_t* js = m.jsched + lane;
+    uint32_t ent = js[0];
+    for (int it = 0; it < m.jit; ++it) {
+      const uint32_t cur = ent;
+      if (it + 1 < m.jit) ent = js[(it + 1) * WAVE];
+      if (cur != ~0u) atomic_add(&v.om[(cur >> 8) & 0xFF], (double)(int8_t)(cur & 0xFF) * v.q[cur >> 16]);
     }
   }
+  lds_wait();
+  wsync();
+  const F om = isSp ? v.om[k] : zero<F>();
   const F Q = wsum(isSp ? hRT * om : zero<F>());
   const F fT = -RU * T * Q / (rho * cp);
   const F fk = isSp ? Wk * om / rho : zero<F>();
@@ -301,6 +322,7 @@ __device__ A vjp_f(const MechView& m, const AdjMech& am, const AdjView<F, A>& v,
   A Tb = uT * fT * iT;
   A hRTb = isSp ? Qb * om : zero<A>();
   if (isSp) v.ob[k] = u * Wk / rho + Qb * hRT;
+  if (lane == 0) v.ob[K] = zero<A>();
   wsync();
   A Tbr = zero<A>();
   for (int r = lane; r < R; r += WAVE) {
@@ -332,6 +354,8 @@ __device__ A vjp_f(const MechView& m, const AdjMech& am, const AdjView<F, A>& v,
     pgr[2] = g2 - part(lnkb * iT);
   }
   wsync();
+  // adjoints of the concentrations and of g/RT: each species lane walks its
+  // incidence and efficiency lists in a fixed order
   A Cb = zero<A>(), gb = zero<A>();
   if (isSp) {
     for (int e = am.sptr[k]; e < am.sptr[k + 1]; ++e) {

@@ -295,27 +295,25 @@ __device__ inline double rhs(const MechView& m, const CellWs& w, double y, doubl
     }
     w.rk[r] = q;
   }
-  wsync();
+  // omega_k = sum_r nu_kr q_r on the balanced species schedule of the
+  // Jacobian pass (every lane takes about L/64 entries), accumulated with LDS
+  // atomics in w.hR, which f does not read (the next thermo pass rewrites it)
   const bool isSp = lane >= 1 && lane <= K;
-  double om = 0.0;
-  if (isSp) {
-    const int k = lane - 1;
-    const int e0 = m.cptr[k], e1 = m.cptr[k + 1];
-    // two independent partial sums, combined in a fixed order
-    double om1 = 0.0;
-    int e = e0;
+  if (isSp) w.hR[lane - 1] = 0.0;
+  wsync();
+  {
+    const uint32_t* js = m.jsched + lane;
+    uint32_t ent = js[0];
 #pragma clang loop unroll(disable)
-    for (; e + 2 <= e1; e += 2) {
-      const uint32_t v0 = m.cent[e], v1 = m.cent[e + 1];
-      om += (double)(int8_t)(v0 & 0xFF) * w.rk[v0 >> 8];
-      om1 += (double)(int8_t)(v1 & 0xFF) * w.rk[v1 >> 8];
+    for (int it = 0; it < m.jit; ++it) {
+      const uint32_t cur = ent;
+      if (it + 1 < m.jit) ent = js[(it + 1) * WAVE];
+      if (cur != ~0u) atomicAdd(w.hR + ((cur >> 8) & 0xFF), (double)(int8_t)(cur & 0xFF) * w.rk[cur >> 16]);
     }
-    if (e < e1) {
-      const uint32_t v0 = m.cent[e];
-      om += (double)(int8_t)(v0 & 0xFF) * w.rk[v0 >> 8];
-    }
-    om += om1;
   }
+  lds_wait();
+  wsync();
+  const double om = isSp ? w.hR[lane - 1] : 0.0;
   const double Q = wave_sum(isSp ? t.hRT * om : 0.0);
   const double fT = -RU * x.T * Q * x.iRho / x.cp;
   wsync();
@@ -440,6 +438,7 @@ __device__ inline double jac_pass(const MechView& m, const CellWs& w, double y, 
       }
     }
   }
+  lds_wait();
   wsync();
   double om = 0.0, dwdT = 0.0, adense = 0.0;
   if (isSp) {
@@ -827,8 +826,9 @@ __device__ void integrate_cell(const MechView& m, const CellWs& w0, const IntArg
       }
       if (fresh && ballot(lane < N && !__builtin_isfinite(f0))) { status = ST_NONFINITE; break; }
       double ynew, err;
-      const int rc = ros_attempt<NP, PROF>(m, w, tab, a.p, lane, y, f0, h, row, ynew, err, mystep, myrdiag, pf,
-                                           nullptr, nullptr, PROF && a.lu_nopiv, formed);
+      int rc = ros_attempt<NP, PROF>(m, w, tab, a.p, lane, y, f0, h, row, ynew, err, mystep, myrdiag, pf, nullptr,
+                                     nullptr, PROF && a.lu_nopiv, formed);
+      if (rc == 0 && c >= a.fail_lu_lo && c < a.fail_lu_hi) rc = 1;  // testing: as if M were singular
       if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
       fresh = false;
       if (rc) {

@@ -95,6 +95,7 @@ struct IntArgs {
   int max_tape, ckpt;
   unsigned long long* prof; // [ncells][8] per-phase cycle counts, or NULL
   unsigned long long* failed; // cells that ended with a nonzero status (counter), or NULL
+  int64_t fail_lu_lo, fail_lu_hi; // cells in [lo, hi) see every factorisation of M as singular (testing)
   int jac_fd;               // ablation (instrumented kernel only): finite-difference Jacobian
   int lu_nopiv;             // ablation (instrumented kernel only): LU without pivoting
 };
@@ -156,6 +157,12 @@ __device__ __forceinline__ unsigned wave_max_u32(unsigned x) {
 
 // Orders the wave's LDS traffic between phases in which lanes read what
 // other lanes wrote.
+// Waits until the wave's outstanding LDS operations (atomics without return
+// included) have completed: s_waitcnt lgkmcnt(0), the other counters at their
+// maximum.  Placed after each loop of LDS atomic accumulations, before the
+// sums are read.
+__device__ __forceinline__ void lds_wait() { __builtin_amdgcn_s_waitcnt(0xc07f); }
+
 __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

@@ -115,6 +115,7 @@ __device__ void integrate_cell_sx(const MechView& m, const CellWs& w, const IntA
           if (l <= j) R[l] = R[l - 1] + (R[l - 1] - P[l - 1]) * ((double)(j + 1 - l) / l);
         }
       }
+      if (rc == 0 && c >= a.fail_lu_lo && c < a.fail_lu_hi) rc = 1;  // testing: as if M were singular
       if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
       fresh = false;
       if (rc) {
@@ -275,6 +276,7 @@ __device__ void wg_integrate_cell_sx(const MechView& m, const WgWs& w, const WgT
           if (l <= j) R[l] = R[l - 1] + (R[l - 1] - P[l - 1]) * ((double)(j + 1 - l) / l);
         }
       }
+      if (rc == 0 && c >= a.fail_lu_lo && c < a.fail_lu_hi) rc = 1;  // testing: as if M were singular
       if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
       fresh = false;
       if (rc) {

@@ -884,7 +884,8 @@ __device__ inline void wg_integrate_cell(const MechView& m, const WgWs& w, const
       ++attempts;
       if (fresh && block_any(t < N && !__builtin_isfinite(f0), w.flag + 1)) { status = ST_NONFINITE; break; }
       double ynew, err;
-      const int rc = wg_attempt<PROF>(m, w, Sx, Mx, NP, tab, a.p, y, f0, h, ynew, err, pf);
+      int rc = wg_attempt<PROF>(m, w, Sx, Mx, NP, tab, a.p, y, f0, h, ynew, err, pf);
+      if (rc == 0 && c >= a.fail_lu_lo && c < a.fail_lu_hi) rc = 1;  // testing: as if M were singular
       if (rc == 2 && fresh) { status = ST_NONFINITE; break; }
       fresh = false;
       if (rc) {

@@ -107,3 +107,27 @@ def test_element_balance_is_validated_on_host(L):
         chem.Mechanism(skip)
     except chem.ChemError as e:
         assert e.code != -1, str(e)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of chem_options, chem_refmap and chem_mech_desc have
+    the C header's size and field offsets (compiled with gcc here)."""
+    import subprocess
+    from paper_2105_12070_amd import chem
+    structs = {"chem_options": chem.Options, "chem_refmap": chem.RefMap, "chem_mech_desc": chem._Desc}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "chem.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
