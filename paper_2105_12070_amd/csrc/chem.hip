@@ -544,6 +544,9 @@ struct chem_mech {
   uint32_t* jsched = nullptr;  // balanced species-scatter schedule of the Jacobian (wavefront path)
   int jsched_it = 0;
   uint32_t* adj_tent = nullptr;
+  uint32_t* adj_chunk = nullptr;  // wavefront path: the sent lists cut into <= 64 chunks, [cw][64]
+  int32_t* adj_cspan = nullptr;   // [K] first chunk | count << 8
+  int adj_cw = 0;
   // workgroup path (64 < N <= 256): Jacobian term lists and per-workgroup scratch
   bool wg = false;
   int wg_np = 0;             // N rounded up to a multiple of 16
@@ -1038,6 +1041,35 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   }
   sptr[K] = (int32_t)sent.size();
   tptr[K] = (int32_t)tent.size();
+  // the sent lists cut into at most 64 chunks of at most cw entries, a
+  // species' chunks consecutive, cw the smallest width that needs <= 64
+  // chunks; chunk j is summed by lane j of the adjoint's gather
+  std::vector<uint32_t> chunk;
+  std::vector<int32_t> cspan(std::max(K, 1), 0);
+  int cw = 0;
+  if (!wg && K > 0) {
+    size_t mx = 0;
+    for (int k = 0; k < K; ++k) mx = std::max(mx, sinc[k].size());
+    cw = (int)std::max<size_t>(mx, 1);
+    for (int w = 1; w <= (int)std::max<size_t>(mx, 1); ++w) {
+      size_t nch = 0;
+      for (int k = 0; k < K; ++k) nch += std::max<size_t>((sinc[k].size() + w - 1) / w, 1);
+      if (nch <= 64) {
+        cw = w;
+        break;
+      }
+    }
+    cw = (cw + 3) / 4 * 4;
+    chunk.assign((size_t)cw * 64, ~0u);
+    int j = 0;
+    for (int k = 0; k < K; ++k) {
+      const int n = (int)sinc[k].size(), nc = std::max((n + cw - 1) / cw, 1);
+      cspan[k] = j | (nc << 8);
+      for (int q = 0; q < nc; ++q, ++j)
+        for (int i = 0; i < cw && q * cw + i < n; ++i) chunk[(size_t)i * 64 + j] = sinc[k][q * cw + i];
+    }
+    if (j > 64) return fail(CHEM_EUNSUPPORTED, "adjoint gather schedule needs more than 64 chunks");
+  }
   if (sent.empty()) sent.push_back(0);
   if (tent.empty()) tent.push_back(0);
   // workgroup-path Jacobian terms: per species row, groups by column, terms in a fixed order
@@ -1107,6 +1139,14 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
       hipMalloc(&m->adj_sptr, 4 * sptr.size()) != hipSuccess || hipMalloc(&m->adj_sent, 4 * sent.size()) != hipSuccess ||
       hipMalloc(&m->adj_tptr, 4 * tptr.size()) != hipSuccess || hipMalloc(&m->adj_tent, 4 * tent.size()) != hipSuccess)
     return cleanup(CHEM_ENOMEM, "device allocation failed");
+  if (!chunk.empty()) {
+    m->adj_cw = cw;
+    if (hipMalloc(&m->adj_chunk, 4 * chunk.size()) != hipSuccess || hipMalloc(&m->adj_cspan, 4 * cspan.size()) != hipSuccess)
+      return cleanup(CHEM_ENOMEM, "device allocation failed");
+    if (hipMemcpy(m->adj_chunk, chunk.data(), 4 * chunk.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->adj_cspan, cspan.data(), 4 * cspan.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(CHEM_EHIP, "upload failed");
+  }
   if (!jsched.empty()) {
     m->jsched_it = (int)(jsched.size() / 64);
     if (hipMalloc(&m->jsched, 4 * jsched.size()) != hipSuccess) return cleanup(CHEM_ENOMEM, "device allocation failed");
@@ -1152,6 +1192,8 @@ void chem_free_mechanism(chem_mech* m) {
   hipFree(m->adj_sent);
   hipFree(m->adj_tptr);
   hipFree(m->adj_tent);
+  hipFree(m->adj_chunk);
+  hipFree(m->adj_cspan);
   hipFree(m->jsched);
   delete m;
 }

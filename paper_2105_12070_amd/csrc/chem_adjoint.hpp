@@ -152,7 +152,8 @@ struct AdjView {
   F* C;   // [66] concentrations (padding species 1)
   F* g;   // [66] g/RT
   F* om;  // [66] production rates omega (accumulated)
-  A* ob;  // [66] adjoint of omega (padding 0)
+  A* ob;  // [66] adjoint of omega (padding 0); then chunk partial sums of the adjoint of C
+  A* xb;  // [64] chunk partial sums of the adjoint of g/RT
   F* q;   // [R] rates of progress (forward part)
   A* aR;  // [R] adjoint of R_f (reverse part; same bytes as q)
   A* aP;  // [R] adjoint of R_r
@@ -163,7 +164,7 @@ template <class F, class A>
 __host__ __device__ inline int adj_doubles(int R, int R0) {
   constexpr int f = (int)(sizeof(F) / sizeof(double)), a = (int)(sizeof(A) / sizeof(double));
   constexpr int qa = f > a ? f : a;
-  return 198 * f + 66 * a + R * qa + R * a + (R - R0 + 1) * a;
+  return 198 * f + 130 * a + R * qa + R * a + (R - R0 + 1) * a;
 }
 
 template <class F, class A>
@@ -175,7 +176,8 @@ __device__ inline AdjView<F, A> make_adj(double* base, int R) {
   v.g = v.C + 66;
   v.om = v.g + 66;
   v.ob = (A*)(base + 198 * f);
-  double* qb = base + 198 * f + 66 * a;
+  v.xb = v.ob + 66;
+  double* qb = base + 198 * f + 130 * a;
   v.q = (F*)qb;
   v.aR = (A*)qb;
   v.aP = (A*)(qb + (size_t)R * qa);
@@ -190,6 +192,11 @@ struct AdjMech {
   const uint32_t* sent; // (r << 3) | slot, slot 0..2 reactants, 3..5 products
   const int32_t* tptr;  // [K+1]
   const uint32_t* tent; // (r << 12) | efficiency entry
+  // the sent lists cut into chunks: chunk[i][j] is entry i of lane j's chunk
+  // (~0 past its end); cspan[k] = first chunk | count << 8 of species k
+  const uint32_t* chunk; // [cw][64]
+  const int32_t* cspan;  // [K]
+  int cw;
 };
 
 template <class S>
@@ -325,9 +332,22 @@ __device__ A vjp_f(const MechView& m, const AdjMech& am, const AdjView<F, A>& v,
   if (lane == 0) v.ob[K] = zero<A>();
   wsync();
   A Tbr = zero<A>();
+  // the gradient accumulators of the lane's next reaction are loaded one
+  // iteration ahead (they live in global memory)
+  double n0 = 0.0, n1 = 0.0, n2 = 0.0;
+  if (lane < R) {
+    n0 = pg[3 * lane];
+    n1 = pg[3 * lane + 1];
+    n2 = pg[3 * lane + 2];
+  }
   for (int r = lane; r < R; r += WAVE) {
     double* pgr = pg + 3 * r;
-    const double g0 = pgr[0], g1 = pgr[1], g2 = pgr[2];
+    const double g0 = n0, g1 = n1, g2 = n2;
+    if (r + WAVE < R) {
+      n0 = pgr[3 * WAVE];
+      n1 = pgr[3 * WAVE + 1];
+      n2 = pgr[3 * WAVE + 2];
+    }
     const RateLoc<F> o = rate_loc<F, A>(m, v, r, T, lnT, iT, Ctot, lnPRT);
     const Slots s = unpack(m.sp[r]);
     const A qb = v.ob[s.p0] + v.ob[s.p1] + v.ob[s.p2] - v.ob[s.r0] - v.ob[s.r1] - v.ob[s.r2];
@@ -354,25 +374,50 @@ __device__ A vjp_f(const MechView& m, const AdjMech& am, const AdjView<F, A>& v,
     pgr[2] = g2 - part(lnkb * iT);
   }
   wsync();
-  // adjoints of the concentrations and of g/RT: each species lane walks its
-  // incidence and efficiency lists in a fixed order
+  // adjoints of the concentrations and of g/RT.  The species' incidence
+  // lists are cut into at most 64 chunks of at most cw entries (a species'
+  // chunks consecutive); lane j sums chunk j in list order, four entries per
+  // pass without branches so that their LDS reads are in flight together;
+  // then every species lane adds its chunks' partial sums in chunk order.
+  A pc = zero<A>(), pgv = zero<A>();
+  {
+    const uint32_t* cg = am.chunk + lane;
+    uint32_t nx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) nx[u] = u < am.cw ? cg[u * WAVE] : ~0u;
+    for (int it = 0; it < am.cw; it += 4) {
+      uint32_t cu[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        cu[u] = nx[u];
+        nx[u] = it + 4 + u < am.cw ? cg[(it + 4 + u) * WAVE] : ~0u;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const bool live = cu[u] != ~0u;
+        const uint32_t ev = live ? cu[u] : 0u;
+        const int r = (int)(ev >> 3), slot = (int)(ev & 7);
+        const bool reac = slot < 3;
+        const Slots s = unpack(m.sp[r]);
+        const A aP = v.aP[r];
+        const A sn = aP * (v.C[s.p0] * v.C[s.p1] * v.C[s.p2]);  // adjoint of sum nu g/RT
+        const int o1 = reac ? (slot == 0 ? s.r1 : s.r0) : (slot == 3 ? s.p1 : s.p0);
+        const int o2 = reac ? (slot == 2 ? s.r1 : s.r2) : (slot == 5 ? s.p1 : s.p2);
+        const A c = (reac ? v.aR[r] : aP) * (v.C[o1] * v.C[o2]);
+        pc += live ? c : zero<A>();
+        pgv += live ? (reac ? -sn : sn) : zero<A>();
+      }
+    }
+  }
+  v.ob[lane] = pc;  // the adjoints of omega are no longer needed
+  v.xb[lane] = pgv;
+  wsync();
   A Cb = zero<A>(), gb = zero<A>();
   if (isSp) {
-    for (int e = am.sptr[k]; e < am.sptr[k + 1]; ++e) {
-      const uint32_t ev = am.sent[e];
-      const int r = (int)(ev >> 3), slot = (int)(ev & 7);
-      const Slots s = unpack(m.sp[r]);
-      const A aP = v.aP[r];
-      const A sn = aP * (v.C[s.p0] * v.C[s.p1] * v.C[s.p2]);  // adjoint of sum nu g/RT
-      if (slot < 3) {
-        const int o1 = slot == 0 ? s.r1 : s.r0, o2 = slot == 2 ? s.r1 : s.r2;
-        Cb += v.aR[r] * (v.C[o1] * v.C[o2]);
-        gb -= sn;
-      } else {
-        const int o1 = slot == 3 ? s.p1 : s.p0, o2 = slot == 5 ? s.p1 : s.p2;
-        Cb += aP * (v.C[o1] * v.C[o2]);
-        gb += sn;
-      }
+    const int c0 = am.cspan[k] & 0xFF, cn = am.cspan[k] >> 8;
+    for (int j = c0; j < c0 + cn; ++j) {
+      Cb += v.ob[j];
+      gb += v.xb[j];
     }
     for (int e = am.tptr[k]; e < am.tptr[k + 1]; ++e) {
       const uint32_t ev = am.tent[e];
