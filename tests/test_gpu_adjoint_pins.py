@@ -2,11 +2,13 @@
 finite differences, entry by entry (53 species / 325 reactions, 975
 Arrhenius parameters).
 
-* Full sensitivity matrix: for single cells, every entry of
-  d Phi(dt) / d (Phi0, lnA, b, theta)  (54 x 1029) from the oracle's
-  tangent-linear replay of its own accepted steps, against the GPU adjoint
-  called once per output component (lambda_final = e_i gives row i: lambda0
-  and the parameter gradient).  |dS| <= 1e-10 max(|S|, 1e-6 max_row |S|).
+* Full sensitivity matrix: every entry of d Phi(dt) / d (Phi0, lnA, b,
+  theta)  (54 x 1029) from the oracle's tangent-linear replay of its own
+  accepted steps, against the GPU adjoint called once per output component
+  (lambda_final = e_i gives row i: lambda0 and the parameter gradient), on 2
+  cells over 2e-10 s (a few hundred steps), |dS| <= 1e-10 max(|S|, 1e-6
+  max_row |S|), and on 64 cells over 2e-11 s, |dS| <= 1e-12 max_row |S| and
+  |dS| <= 1e-11 |S| where |S| >= 1e-3 max_row |S|.
 * All 975 parameters on 32 cells: the gradient of Psi = sum_cells
   [T + w.Y](dt) against central differences with replayed step sizes
   (tests/golden/make_adjoint_fd.py, oracle only), |dg| <= 1e-5 max(|g|,
@@ -87,6 +89,61 @@ def test_full_sensitivity_matrix(chem):
         say(f"[cell {c}] max |dS| / scale {ratio.max():.3e} (state block {ratio[:, :N].max():.3e}, "
             f"parameter block {ratio[:, N:].max():.3e}) over {S.size} entries")
         assert ratio.max() <= 1e-10, np.unravel_index(np.argmax(ratio), ratio.shape)
+
+
+@pytest.mark.timeout(900)
+def test_full_sensitivity_matrix_64_cells(chem):
+    """The whole 54 x 1,029 matrix on 64 cells spread over the workload's 16,384, over dt = 2e-11 s (50 to 200 steps
+    each, so that the oracle's 64 matrices take minutes): one single-cell adjoint call per output component and cell
+    (lambda_final = e_i gives row i), every entry against the oracle's tangent-linear matrix.
+
+    The adjoint and the tangent-linear replay sum the same chain-rule terms in opposite orders, so the rounding error
+    of an entry follows the size of the terms of its row, not of the entry: an entry that is the small difference of
+    large terms carries an absolute error of a few ulps of the row's largest entry.  Two bounds: |dS| <= 1e-12
+    max_row |S| on every entry, and |dS| <= 1e-11 |S| on entries of at least 1e-3 max_row |S|."""
+    w = WORKLOADS["c4_adj"]
+    mech = w.mechanism()
+    m = chem.Mechanism(mech)
+    om = oracle.Mech(mech)
+    dt = 2e-11
+    N = w.N
+    idx = np.linspace(0, w.n_cells - 1, 64).astype(np.int64)
+    st = np.ascontiguousarray(w.states(mech, w.n_cells)[:, idx])
+    worst_abs, worst_rel, compared = 0.0, 0.0, 0
+    for c in range(st.shape[1]):
+        y, h, hs, status, _ = oracle.integrate_record(om, st[:, c], None, w.p_pa, dt, w.rtol, w.atol)
+        assert status == 0
+        S = oracle.tlm_matrix(om, st[:, c], hs, w.p_pa)
+        G = np.zeros_like(S)
+        same = True
+        for i in range(N):
+            lam = np.zeros((N, 1))
+            lam[i, 0] = 1.0
+            lam0, grad, steps, stat = _adjoint(chem, m, st[:, c:c + 1], w, dt, lam)
+            assert stat[0] == 0
+            if steps[0] != len(hs):
+                same = False
+                break
+            G[i, :N] = lam0[:, 0]
+            G[i, N:] = grad
+        if not same:
+            say(f"[cell {idx[c]}] step count differs from the oracle's ({len(hs)}): not compared")
+            continue
+        rowmax = np.abs(S).max(axis=1, keepdims=True)
+        d = np.abs(G - S)
+        ab = (d / rowmax).max()
+        big = np.abs(S) >= 1e-3 * rowmax
+        rel = (d[big] / np.abs(S[big])).max()
+        worst_abs, worst_rel = max(worst_abs, ab), max(worst_rel, rel)
+        compared += 1
+        if c % 8 == 0:
+            say(f"[cell {idx[c]}] {len(hs)} steps, max |dS| / max_row |S| {ab:.3e}, relative on the large entries "
+                f"{rel:.3e}")
+    say(f"64 cells: {compared} compared ({compared * N * (N + 3 * w.n_reactions)} entries), max |dS| / max_row |S| "
+        f"{worst_abs:.3e}, max |dS| / |S| where |S| >= 1e-3 max_row |S|: {worst_rel:.3e}")
+    assert compared >= 56
+    assert worst_abs <= 1e-12
+    assert worst_rel <= 1e-11
 
 
 @pytest.fixture(scope="module")
