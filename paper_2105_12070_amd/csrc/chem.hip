@@ -223,6 +223,7 @@ __global__ __launch_bounds__(WG, 2) void k_integrate_wg(IntArgs a, WgTerms tl, d
   double* Sx = scratch + (size_t)blockIdx.x * 2 * NP * NP;
   double* Mx = Sx + (size_t)NP * NP;
   for (int i = threadIdx.x; i < NP * NP; i += WG) Sx[i] = 0.0;
+  for (int i = threadIdx.x; i < wg_ntb(a.d); i += WG) w.tbd[i] = m.tbd[i];
   __syncthreads();
   if (threadIdx.x == 0) w.flag[3] = atomicAdd(a.queue, 1);
   __syncthreads();
@@ -249,6 +250,7 @@ __global__ __launch_bounds__(WG, 2) void k_integrate_wg_sx(IntArgs a, WgTerms tl
   double* Sx = scratch + (size_t)blockIdx.x * 2 * NP * NP;
   double* Mx = Sx + (size_t)NP * NP;
   for (int i = threadIdx.x; i < NP * NP; i += WG) Sx[i] = 0.0;
+  for (int i = threadIdx.x; i < wg_ntb(a.d); i += WG) w.tbd[i] = m.tbd[i];
   __syncthreads();
   if (threadIdx.x == 0) w.flag[3] = atomicAdd(a.queue, 1);
   __syncthreads();
@@ -272,6 +274,7 @@ __global__ __launch_bounds__(WG) void k_rhs_jac_wg(IntArgs a, WgTerms tl, double
   const WgWs w = make_wg_ws((double*)lds, a.d.R, NP);
   double* Sx = scratch + (size_t)blockIdx.x * NP * NP;
   for (int i = threadIdx.x; i < NP * NP; i += WG) Sx[i] = 0.0;
+  for (int i = threadIdx.x; i < wg_ntb(a.d); i += WG) w.tbd[i] = m.tbd[i];
   __syncthreads();
   const int t = threadIdx.x, N = m.d.N;
   for (int64_t c = blockIdx.x; c < a.ncells; c += gridDim.x) {
@@ -605,7 +608,9 @@ int set_lds_limit(const void* fn, size_t bytes) {
 
 // LDS of the workgroup-path kernels (workspace only: they read the
 // mechanism tables from global memory)
-size_t wg_lds_bytes(const chem_mech* m) { return (size_t)wg_ws_doubles(m->d.R, m->wg_np) * sizeof(double); }
+size_t wg_lds_bytes(const chem_mech* m) {
+  return (size_t)wg_ws_doubles(m->d.R, m->wg_np, wg_ntb(m->d)) * sizeof(double);
+}
 
 WgTerms wg_terms(const chem_mech* m) {
   WgTerms t;
@@ -1499,7 +1504,7 @@ static int lu_wg_launch(int64_t nmat, int32_t n, const double* A, double* b, int
   double* scr = nullptr;
   if (hipMalloc(&scr, sizeof(double) * (size_t)grid * NP * NP) != hipSuccess)
     return fail(CHEM_ENOMEM, "LU scratch allocation failed");
-  const size_t lds = (size_t)wg_ws_doubles(0, NP) * sizeof(double);
+  const size_t lds = (size_t)wg_ws_doubles(0, NP, 0) * sizeof(double);
   hipError_t e = hipFuncSetAttribute((const void*)k_lu_wg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_lu_wg, dim3(grid), dim3(WG), lds, (hipStream_t)stream, nmat, n, A, b, info, scr, NP, LU,

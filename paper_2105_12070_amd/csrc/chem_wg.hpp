@@ -40,6 +40,7 @@ struct WgTerms {
 // Per-workgroup LDS workspace (beyond the staged mechanism blob); NP = N
 // rounded up to a multiple of 16.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 struct WgWs {
   double* C;     // [NP] concentrations, C[K] = 1
@@ -63,13 +64,18 @@ struct WgWs {
   int* flag;     // [4] flags and the queue broadcast; [4] interchange count of the panel
   int* sdst;     // [32] rows written by the panel's interchanges
   int* ssrc;     // [32] the rows they take their values from
+  double* tbd;   // [ntb] third-body efficiencies - 1 (a copy of the mechanism's)
 };
 
+// Doubles of the mechanism's efficiency table (as laid out in the blob).
+__host__ __device__ inline int wg_ntb(const MechDims& d) { return (d.o_troe - d.o_tbd) / 8; }
+
 // The Jacobian's rate arrays rkr, rdm, rdt and the LU's panel buffers Pn, Ub
-// are never live at the same time, so they share one region.
-__host__ __device__ inline int wg_ws_doubles(int R, int NP) {
+// are never live at the same time, so they share one region.  ntb: doubles of
+// the efficiency table copied to the end (0 where no Jacobian is formed).
+__host__ __device__ inline int wg_ws_doubles(int R, int NP, int ntb) {
   const int shared = 2 * WNB * NP > 3 * R ? 2 * WNB * NP : 3 * R;
-  return 3 * NP + R + 5 * NP + shared + NP + 16 + NP / 2 + NP / 2 + 40;
+  return 3 * NP + R + 5 * NP + shared + NP + 16 + NP / 2 + NP / 2 + 40 + ntb;
 }
 
 __device__ inline WgWs make_wg_ws(double* base, int R, int NP) {
@@ -97,6 +103,7 @@ __device__ inline WgWs make_wg_ws(double* base, int R, int NP) {
   w.flag = w.perm + NP;
   w.sdst = w.flag + 8;
   w.ssrc = w.sdst + 32;
+  w.tbd = (double*)w.piv + NP + 40;  // past the 2 NP + 72 ints above
   return w;
 }
 
@@ -203,11 +210,19 @@ __device__ inline double wg_rhs(const MechView& m, const WgWs& w, double y, doub
   const bool isSp = t >= 1 && t <= K;
   double om = 0.0;
   if (isSp) {
-    const int k = t - 1;
+    // the incidence list is in global memory: eight entries per pass, loaded
+    // together, then summed in list order
+    const int k = t - 1, e0 = m.cptr[k], e1 = m.cptr[k + 1];
 #pragma clang loop unroll(disable)
-    for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
-      const uint32_t v = m.cent[e];
-      om += (double)(int8_t)(v & 0xFF) * w.rk[v >> 8];
+    for (int eb = e0; eb < e1; eb += 8) {
+      uint32_t v8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v8[u] = eb + u < e1 ? m.cent[eb + u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (eb + u >= e1) break;
+        om += (double)(int8_t)(v8[u] & 0xFF) * w.rk[v8[u] >> 8];
+      }
     }
   }
   const double Q = block_sum(isSp ? th.hRT * om : 0.0, w.red);
@@ -266,16 +281,27 @@ __device__ inline double wg_jac(const MechView& m, const WgWs& w, const WgTerms&
   const bool isSp = t >= 1 && t <= K;
   double om = 0.0, dwdT = 0.0, adense = 0.0, sk = 0.0;
   if (isSp) {
-    const int k = t - 1;
+    const int k = t - 1, e0 = m.cptr[k], e1 = m.cptr[k + 1];
+    // incidence entries and their reactions' slots come from global memory:
+    // eight per pass, loaded together, then summed in list order
 #pragma clang loop unroll(disable)
-    for (int e = m.cptr[k]; e < m.cptr[k + 1]; ++e) {
-      const uint32_t v = m.cent[e];
-      const int r = (int)(v >> 8);
-      const double nu = (double)(int8_t)(v & 0xFF);
-      const Slots s = unpack(m.sp[r]);
-      om += nu * (w.rk[r] * w.C[s.r0] * w.C[s.r1] * w.C[s.r2] - w.rkr[r] * w.C[s.p0] * w.C[s.p1] * w.C[s.p2]);
-      dwdT += nu * w.rdt[r];
-      if (r >= m.d.R0) adense += nu * w.rdm[r];
+    for (int eb = e0; eb < e1; eb += 8) {
+      uint32_t v8[8];
+      uint64_t sp8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v8[u] = eb + u < e1 ? m.cent[eb + u] : 0u;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sp8[u] = eb + u < e1 ? m.sp[v8[u] >> 8] : 0ull;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (eb + u >= e1) break;
+        const int r = (int)(v8[u] >> 8);
+        const double nu = (double)(int8_t)(v8[u] & 0xFF);
+        const Slots s = unpack(sp8[u]);
+        om += nu * (w.rk[r] * w.C[s.r0] * w.C[s.r1] * w.C[s.r2] - w.rkr[r] * w.C[s.p0] * w.C[s.p1] * w.C[s.p2]);
+        dwdT += nu * w.rdt[r];
+        if (r >= m.d.R0) adense += nu * w.rdm[r];
+      }
     }
     // structural nonzeros of row k, one group per column, terms in a fixed order
     double* Srow = Sx + (size_t)t * NP + 1;
@@ -284,25 +310,38 @@ __device__ inline double wg_jac(const MechView& m, const WgWs& w, const WgTerms&
     // the last term of each column group carries the column and closes it
     const int tb = (int)(tl.grp[g0] >> 8), te = (int)(tl.grp[g1] >> 8);
     double acc = 0.0;
+    // software-pipelined: the next pass's term words are in flight while this
+    // pass is summed; the pass itself has no branch except the column store
+    uint64_t nx[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) nx[u] = tb + u < te ? tl.term[tb + u] : 0ull;
 #pragma clang loop unroll(disable)
     for (int ti = tb; ti < te; ti += 8) {
       uint64_t tw8[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) tw8[u] = ti + u < te ? tl.term[ti + u] : 0ull;
+      for (int u = 0; u < 8; ++u) {
+        tw8[u] = nx[u];
+        nx[u] = ti + 8 + u < te ? tl.term[ti + 8 + u] : 0ull;
+      }
+      // the efficiencies of third-body terms (from the LDS copy)
+      double ef8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        ef8[u] = (ti + u < te && ((tw8[u] >> 16) & 7) == 6) ? w.tbd[(tw8[u] >> 48) & 0xFFF] : 0.0;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        if (ti + u >= te) break;
+        const bool in = ti + u < te;  // past the row's end the word is 0: indices 0, no store
         const uint64_t tw = tw8[u];
         const int r = (int)(tw & 0xFFFF);
         const int kind = (int)((tw >> 16) & 7);
         const double nu = (double)(int8_t)((tw >> 24) & 0xFF);
         const double co = w.C[(tw >> 32) & 0xFF] * w.C[(tw >> 40) & 0xFF];
-        double v;
-        if (kind < 3) v = w.rk[r] * co;
-        else if (kind < 6) v = -w.rkr[r] * co;
-        else v = w.rdm[r] * m.tbd[(tw >> 48) & 0xFFF];
-        acc += nu * v;
-        if ((tw >> 19) & 1) {
+        // one rate load per term: the array is picked by the kind
+        const double rv = (kind < 3 ? w.rk : (kind < 6 ? w.rkr : w.rdm))[r];
+        const double v = (kind >= 3 && kind < 6 ? -rv : rv) * (kind < 6 ? co : ef8[u]);
+        const double an = acc + nu * v;
+        acc = in ? an : acc;
+        if (in && ((tw >> 19) & 1)) {
           const int col = (int)(((tw >> 20) & 0xF) | (((tw >> 60) & 0xF) << 4));
           Srow[col] = acc;
           sk += w.C[col] * acc;
@@ -372,33 +411,53 @@ __device__ inline double wg_jac(const MechView& m, const WgWs& w, const WgTerms&
 // false if an entry is not finite.
 __device__ inline bool wg_form(const MechView& m, const WgWs& w, const double* Sx, double* Mx, int NP, double d) {
   const int N = m.d.N, tot = NP * NP;
+  // Thread t forms the element pairs (idx, idx + 1), idx = 2t + 2 WG u (NP is
+  // even, so a pair never leaves its row).  Row and column follow idx by
+  // additions; eight pairs per pass have their scratch loads in flight
+  // together.
+  constexpr int STEP = 2 * WG;
+  const int di = STEP / NP, dj = STEP - di * NP;
+  int i = (2 * (int)threadIdx.x) / NP, j = 2 * (int)threadIdx.x - i * NP;
   bool bad = false;
-  // eight elements per pass: their scratch loads are in flight together
 #pragma clang loop unroll(disable)
-  for (int base = threadIdx.x; base < tot; base += 8 * WG) {
-    double sv[8];
+  for (int base = 2 * (int)threadIdx.x; base < tot; base += 8 * STEP) {
+    dbl2 sv[8];
+    int ri[8], cj[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int idx = base + u * WG;
-      sv[u] = idx < tot ? Sx[idx] : 0.0;
+      const int idx = base + u * STEP;
+      ri[u] = i;
+      cj[u] = j;
+      sv[u] = idx < tot ? *(const dbl2*)(Sx + idx) : dbl2{0.0, 0.0};
+      j += dj;
+      i += di;
+      if (j >= NP) {
+        j -= NP;
+        ++i;
+      }
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int idx = base + u * WG;
+      const int idx = base + u * STEP;
       if (idx >= tot) break;
-      const int i = idx / NP, j = idx - i * NP;
-      double v;
-      if (i >= N || j >= N) {
-        v = i == j ? 1.0 : 0.0;
-      } else {
-        double J;
-        if (i == 0) J = w.jTr[j];
-        else if (j == 0) J = w.jT0[i];
-        else J = m.iW[j - 1] * (m.W[i - 1] * (sv[u] + w.ad[i]) + w.gam[i]);
-        v = (i == j ? d : 0.0) - J;
-        bad |= !__builtin_isfinite(v);
+      const int r = ri[u];
+      double v[2];
+      const double sr[2] = {sv[u][0], sv[u][1]};
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int c = cj[u] + e;
+        if (r >= N || c >= N) {
+          v[e] = r == c ? 1.0 : 0.0;
+        } else {
+          double J;
+          if (r == 0) J = w.jTr[c];
+          else if (c == 0) J = w.jT0[r];
+          else J = m.iW[c - 1] * (m.W[r - 1] * (sr[e] + w.ad[r]) + w.gam[r]);
+          v[e] = (r == c ? d : 0.0) - J;
+          bad |= !__builtin_isfinite(v[e]);
+        }
       }
-      Mx[idx] = v;
+      *(dbl2*)(Mx + idx) = dbl2{v[0], v[1]};
     }
   }
   return !block_any(bad, w.flag + 1);
@@ -701,15 +760,19 @@ __device__ inline int wg_lu(const WgWs& w, double* Mx, int NP, Prof<PROF>* pf = 
     }
     __syncthreads();
   }
-  // composition of the interchanges: row i of P M is row perm[i] of M
-  if (t == 0) {
-    for (int i = 0; i < NP; ++i) w.perm[i] = i;
-    for (int k = 0; k < NP; ++k) {
-      const int pr = w.piv[k];
-      const int a = w.perm[k];
-      w.perm[k] = w.perm[pr];
-      w.perm[pr] = a;
+  // composition of the interchanges: row i of P M is row perm[i] of M.
+  // Thread i follows its row back through the interchanges, last first.
+  if (t < NP) {
+    int pos = t;
+#pragma clang loop unroll(disable)
+    for (int k0 = NP - WNB; k0 >= 0; k0 -= WNB) {
+      int q[WNB];
+#pragma unroll
+      for (int u = 0; u < WNB; ++u) q[u] = w.piv[k0 + u];
+#pragma unroll
+      for (int u = WNB - 1; u >= 0; --u) pos = pos == k0 + u ? q[u] : (pos == q[u] ? k0 + u : pos);
     }
+    w.perm[t] = pos;
   }
   __syncthreads();
   const int info = w.flag[2];
@@ -755,11 +818,12 @@ __device__ inline double wg_solve(const WgWs& w, const double* Mx, int NP, doubl
       if (inb) w.vec[t] = y;
     }
     __syncthreads();
+    // no barrier after this update: the next block's diagonal wave writes
+    // other entries of vec, and it updates its own rows here first
     if (t >= pn && t < NP) {
 #pragma unroll
       for (int c = 0; c < WNB; ++c) y = fma(-seg[c], w.vec[p0 + c], y);
     }
-    __syncthreads();
   }
   // back substitution with U, last block first
   const int last = NP - WNB;
@@ -793,7 +857,6 @@ __device__ inline double wg_solve(const WgWs& w, const double* Mx, int NP, doubl
 #pragma unroll
       for (int c = 0; c < WNB; ++c) y = fma(-seg[c], w.vec[p0 + c], y);
     }
-    __syncthreads();
   }
   return t < NP ? y : 0.0;
 }
