@@ -23,6 +23,11 @@ Psi = sum_cells [T + sum_k w_k Y_k](dt) with the seeded weights w.  Steps:
 The oracle's step counts per cell are stored so that the GPU test compares
 only cells whose adjoint takes the same steps.  Only the oracle is called.
 Run from the repository root:  python tests/golden/make_adjoint_fd.py
+
+With the argument "all-cells" it writes adjoint_tlm_all.npz instead: the same
+20 parameters' tangent-linear derivatives of each cell's objective on all
+16,384 cells of the workload (the generator's 16,384-cell draw, which is not
+an extension of its 1,024-cell one), with the oracle's step counts.
 """
 import hashlib
 import json
@@ -39,7 +44,9 @@ sys.path.insert(0, ROOT)
 import oracle  # noqa: E402
 from paper_2105_12070_amd.inputs import WORKLOADS, objective_weights  # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_fd.npz")
+HERE = os.path.dirname(os.path.abspath(__file__))
+OUT = os.path.join(HERE, "adjoint_fd.npz")
+OUT_ALL = os.path.join(HERE, "adjoint_tlm_all.npz")
 DT = 2e-10
 
 
@@ -67,6 +74,52 @@ def tlm_column(mech, w, st, recs, weights, kind, r, cells):
                      for c in cells])
 
 
+def pick_parameters(R):
+    rng = np.random.default_rng(4005)
+    return np.sort(rng.choice(3 * R, 20, replace=False))
+
+
+def cell_tlm_row(mech, om, w, y0, weights, pick):
+    """One cell: record its accepted steps, then d Psi_c / d p for each picked parameter."""
+    R = mech["n_reactions"]
+    rec = oracle.integrate_record(om, y0, None, w.p_pa, DT, w.rtol, w.atol)
+    assert rec[3] == 0
+    row = np.zeros(len(pick))
+    for j, q in enumerate(pick):
+        d = [np.zeros(R), np.zeros(R), np.zeros(R)]
+        d[q // R][q % R] = 1.0
+        row[j] = oracle.tlm(om, y0, rec[2], w.p_pa, dlnA=d[0], db=d[1], dtheta=d[2])[1] @ weights
+    return len(rec[2]), row
+
+
+def main_all_cells():
+    w = WORKLOADS["c4_adj"]
+    mech = w.mechanism()
+    weights = np.concatenate([[1.0], objective_weights(w.n_species)])
+    st = w.states(mech, w.n_cells)
+    om = oracle.Mech(mech)
+    pick = pick_parameters(mech["n_reactions"])
+    t0 = time.time()
+    out = [None] * w.n_cells
+
+    def work(c):
+        out[c] = cell_tlm_row(mech, om, w, st[:, c], weights, pick)
+        if c % 1024 == 0:
+            print(f"cell {c}: {time.time() - t0:.0f} s", flush=True)
+
+    with ThreadPoolExecutor(os.cpu_count() or 8) as ex:
+        list(ex.map(work, range(w.n_cells)))
+    steps = np.array([o[0] for o in out], dtype=np.int32)
+    tlm = np.stack([o[1] for o in out])  # [n_cells, 20]
+    np.savez(OUT_ALL, steps=steps, pick=pick, tlm=tlm)
+    meta = {"dt": DT, "rtol": w.rtol, "atol": w.atol, "n_cells": w.n_cells,
+            "input_sha256": hashlib.sha256(st.tobytes()).hexdigest(),
+            "steps_min_max": [int(steps.min()), int(steps.max())], "seconds": round(time.time() - t0, 1)}
+    with open(OUT_ALL.replace(".npz", ".json"), "w") as f:
+        json.dump(meta, f, indent=1)
+    print(json.dumps(meta))
+
+
 def main():
     w = WORKLOADS["c4_adj"]
     mech = w.mechanism()
@@ -83,8 +136,7 @@ def main():
         cells32 = list(range(32))
         cols = list(ex.map(lambda q: fd_column(mech, w, st, recs, weights, q // R, q % R, cells32), range(3 * R)))
         all32 = np.stack(cols, axis=1)  # [32 cells, 3R]
-        rng = np.random.default_rng(4005)
-        pick = np.sort(rng.choice(3 * R, 20, replace=False))
+        pick = pick_parameters(R)
         cells1k = list(range(1024))
         cols = list(ex.map(lambda q: fd_column(mech, w, st, recs, weights, q // R, q % R, cells1k), pick))
         rand1k = np.stack(cols, axis=1)  # [1024 cells, 20]
@@ -99,4 +151,7 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "all-cells":
+        main_all_cells()
+    else:
+        main()

@@ -17,7 +17,9 @@ Arrhenius parameters).
   derivative of the same replays, |dg| <= 1e-9 max(|g|, 1e-6 max|g|) (summed
   over 1,024 cells, the central differences' rounding noise, ~1e-4 absolute,
   exceeds the difference bound for the smallest entries; their deviation is
-  reported).
+  reported).  The same 20 parameters on all 16,384 cells of the workload
+  against the oracle's tangent-linear derivatives (make_adjoint_fd.py
+  all-cells), same bound.
 Cells are compared only where the GPU takes the oracle's number of steps (the
 adjoint differentiates the GPU's own step sequence).
 """
@@ -198,3 +200,27 @@ def test_random_parameters_1024_cells(chem, fd):
         f"(max |g| {np.abs(fdv).max():.3e})")
     ref = fd[0]["tlm1k"][same].sum(axis=0)
     _fd_check(grad[pick], ref, "20 parameters, 1,024 cells, tangent-linear", rel=1e-9, floor=1e-6)
+
+
+def test_random_parameters_all_cells(chem):
+    with np.load(os.path.join(HERE, "golden", "adjoint_tlm_all.npz"), allow_pickle=False) as z:
+        g = {k: z[k] for k in z.files}
+    with open(os.path.join(HERE, "golden", "adjoint_tlm_all.json")) as f:
+        meta = json.load(f)
+    w = WORKLOADS["c4_adj"]
+    mech = w.mechanism()
+    st = w.states(mech, w.n_cells)
+    assert hashlib.sha256(st.tobytes()).hexdigest() == meta["input_sha256"], "input generator changed"
+    n = st.shape[1]
+    weights = np.concatenate([[1.0], objective_weights(w.n_species)])
+    m = chem.Mechanism(mech)
+    lam = np.repeat(weights[:, None], n, axis=1)
+    _, _, steps, status = _adjoint(chem, m, st, w, meta["dt"], lam)
+    assert np.all(status == 0)
+    same = steps == g["steps"]
+    say(f"{n} cells: {same.sum()} with the oracle's step count")
+    assert same.sum() >= 0.9 * n
+    lam[:, ~same] = 0.0
+    _, grad, _, _ = _adjoint(chem, m, st, w, meta["dt"], lam)
+    ref = g["tlm"][same].sum(axis=0)
+    _fd_check(grad[g["pick"]], ref, f"20 parameters, {n} cells, tangent-linear", rel=1e-9, floor=1e-6)
