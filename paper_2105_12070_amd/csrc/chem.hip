@@ -1001,7 +1001,7 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   d.o_tbp = take(4 * tbp.size());
   d.o_tbs = take(4 * std::max<size_t>(tbs.size(), 1));
   d.o_tbd = take(8 * std::max<size_t>(tbd.size(), 1));
-  d.o_troe = take(8 * std::max<size_t>(troe.size(), 1));
+  d.o_troe = take(8 * std::max<size_t>(troe.size(), 1));  // right after tbd: wg_ntb counts tbd from the gap
   d.lds_bytes = (int)off;
   std::vector<uint8_t> blob(off, 0);
   for (int ri = 0; ri < R; ++ri) {
