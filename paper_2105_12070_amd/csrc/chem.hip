@@ -556,6 +556,7 @@ struct chem_mech {
   int32_t* wg_gptr = nullptr;
   uint32_t* wg_grp = nullptr;
   uint64_t* wg_term = nullptr;
+  int32_t* wg_seg = nullptr;  // [WG][4] term segment per thread (first, end, row, partner)
   double* wg_scr = nullptr;
   size_t wg_scr_bytes = 0;
 };
@@ -617,6 +618,7 @@ WgTerms wg_terms(const chem_mech* m) {
   t.gptr = m->wg_gptr;
   t.grp = m->wg_grp;
   t.term = m->wg_term;
+  t.seg = m->wg_seg;
   return t;
 }
 
@@ -1081,6 +1083,7 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
   std::vector<int32_t> wgptr;
   std::vector<uint32_t> wgrp;
   std::vector<uint64_t> wterm;
+  std::vector<int32_t> wseg;
   if (wg) {
     wgptr.assign(K + 1, 0);
     for (int k = 0; k < K; ++k) {
@@ -1112,6 +1115,47 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
     wgrp.push_back((uint32_t)wterm.size() << 8);
     if (wterm.size() >= (1u << 24)) return fail(CHEM_EUNSUPPORTED, "too many Jacobian terms");
     if (wterm.empty()) wterm.push_back(0);
+    // term segments: thread 1 + k sums row k; the threads that own no row
+    // (0 and K+1 ..) take the second half of the longest rows, split at the
+    // column group that best balances the two halves
+    wseg.assign(4 * WG, -1);
+    auto gstart = [&](int g) { return (int32_t)(wgrp[g] >> 8); };
+    std::vector<int> byLen(K);
+    for (int k = 0; k < K; ++k) {
+      byLen[k] = k;
+      int32_t* q = &wseg[4 * (1 + k)];
+      q[0] = gstart(wgptr[k]);
+      q[1] = gstart(wgptr[k + 1]);
+      q[2] = k;
+    }
+    std::stable_sort(byLen.begin(), byLen.end(), [&](int x, int y) {
+      return gstart(wgptr[x + 1]) - gstart(wgptr[x]) > gstart(wgptr[y + 1]) - gstart(wgptr[y]);
+    });
+    int next = 0;
+    for (int sp = 0; sp < WG; ++sp) {
+      if (sp >= 1 && sp <= K) continue;
+      if (next >= K) break;
+      const int k = byLen[next++];
+      const int32_t tb = gstart(wgptr[k]), te = gstart(wgptr[k + 1]);
+      int best = -1;
+      int32_t bestw = te - tb;
+      for (int g = wgptr[k] + 1; g < wgptr[k + 1]; ++g) {
+        const int32_t wmax = std::max(gstart(g) - tb, te - gstart(g));
+        if (wmax < bestw) {
+          bestw = wmax;
+          best = g;
+        }
+      }
+      if (best < 0) continue;  // a single column group stays whole
+      int32_t* q = &wseg[4 * (1 + k)];
+      q[1] = gstart(best);
+      q[3] = sp;
+      int32_t* r = &wseg[4 * sp];
+      r[0] = gstart(best);
+      r[1] = te;
+      r[2] = k;
+      r[3] = -1;
+    }
   }
   chem_mech* m = new chem_mech();
   m->d = d;
@@ -1132,11 +1176,12 @@ int chem_load_mechanism(const chem_mech_desc* desc, chem_mech** out) {
     return cleanup(CHEM_EUNSUPPORTED, "the workgroup workspace needs more LDS than a workgroup has");
   if (wg) {
     if (hipMalloc(&m->wg_gptr, 4 * wgptr.size()) != hipSuccess || hipMalloc(&m->wg_grp, 4 * wgrp.size()) != hipSuccess ||
-        hipMalloc(&m->wg_term, 8 * wterm.size()) != hipSuccess)
+        hipMalloc(&m->wg_term, 8 * wterm.size()) != hipSuccess || hipMalloc(&m->wg_seg, 4 * wseg.size()) != hipSuccess)
       return cleanup(CHEM_ENOMEM, "device allocation failed");
     if (hipMemcpy(m->wg_gptr, wgptr.data(), 4 * wgptr.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(m->wg_grp, wgrp.data(), 4 * wgrp.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(m->wg_term, wterm.data(), 8 * wterm.size(), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(m->wg_term, wterm.data(), 8 * wterm.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(m->wg_seg, wseg.data(), 4 * wseg.size(), hipMemcpyHostToDevice) != hipSuccess)
       return cleanup(CHEM_EHIP, "upload failed");
   }
   if (hipMalloc(&m->blob, blob.size()) != hipSuccess || hipMalloc(&m->nasa, 8 * nasa.size()) != hipSuccess ||
@@ -1192,6 +1237,7 @@ void chem_free_mechanism(chem_mech* m) {
   hipFree(m->wg_gptr);
   hipFree(m->wg_grp);
   hipFree(m->wg_term);
+  hipFree(m->wg_seg);
   hipFree(m->wg_scr);
   hipFree(m->adj_sptr);
   hipFree(m->adj_sent);

@@ -35,6 +35,11 @@ struct WgTerms {
   const int32_t* gptr;  // [K+1]
   const uint32_t* grp;  // [G+1] (sentinel at G)
   const uint64_t* term; // [T]
+  // [WG][4] the term segment of thread t: first term, end, row (-1: none) and,
+  // for the thread that owns a row, the thread holding the row's second
+  // segment (-1: the row is not split).  Rows are split at a column group, so
+  // each Sx entry comes from one segment.
+  const int32_t* seg;
 };
 
 // Per-workgroup LDS workspace (beyond the staged mechanism blob); NP = N
@@ -64,6 +69,7 @@ struct WgWs {
   int* flag;     // [4] flags and the queue broadcast; [4] interchange count of the panel
   int* sdst;     // [32] rows written by the panel's interchanges
   int* ssrc;     // [32] the rows they take their values from
+  double* skp;   // [WG] partial sums C . S_row of the term segments
   double* tbd;   // [ntb] third-body efficiencies - 1 (a copy of the mechanism's)
 };
 
@@ -75,7 +81,7 @@ __host__ __device__ inline int wg_ntb(const MechDims& d) { return (d.o_troe - d.
 // the efficiency table copied to the end (0 where no Jacobian is formed).
 __host__ __device__ inline int wg_ws_doubles(int R, int NP, int ntb) {
   const int shared = 2 * WNB * NP > 3 * R ? 2 * WNB * NP : 3 * R;
-  return 3 * NP + R + 5 * NP + shared + NP + 16 + NP / 2 + NP / 2 + 40 + ntb;
+  return 3 * NP + R + 5 * NP + shared + NP + 16 + NP / 2 + NP / 2 + 40 + WG + ntb;
 }
 
 __device__ inline WgWs make_wg_ws(double* base, int R, int NP) {
@@ -103,7 +109,8 @@ __device__ inline WgWs make_wg_ws(double* base, int R, int NP) {
   w.flag = w.perm + NP;
   w.sdst = w.flag + 8;
   w.ssrc = w.sdst + 32;
-  w.tbd = (double*)w.piv + NP + 40;  // past the 2 NP + 72 ints above
+  w.skp = (double*)w.piv + NP + 40;  // past the 2 NP + 72 ints above
+  w.tbd = w.skp + WG;
   return w;
 }
 
@@ -303,52 +310,65 @@ __device__ inline double wg_jac(const MechView& m, const WgWs& w, const WgTerms&
         if (r >= m.d.R0) adense += nu * w.rdm[r];
       }
     }
-    // structural nonzeros of row k, one group per column, terms in a fixed order
-    double* Srow = Sx + (size_t)t * NP + 1;
-    const int g0 = tl.gptr[k], g1 = tl.gptr[k + 1];
-    // the row's terms are contiguous; eight term words are loaded per pass and
-    // the last term of each column group carries the column and closes it
-    const int tb = (int)(tl.grp[g0] >> 8), te = (int)(tl.grp[g1] >> 8);
-    double acc = 0.0;
-    // software-pipelined: the next pass's term words are in flight while this
-    // pass is summed; the pass itself has no branch except the column store
-    uint64_t nx[8];
+  }
+  // structural nonzeros, one group per column, terms in a fixed order: thread
+  // t sums its segment of a row's terms (the loader splits the longest rows
+  // in two at a column group and gives the second halves to the threads that
+  // own no row)
+  {
+    typedef int int4v __attribute__((ext_vector_type(4)));
+    const int4v sg = *(const int4v*)(tl.seg + 4 * t);
+    const int tb = sg[0], te = sg[1], srow = sg[2];
+    double skt = 0.0;
+    if (srow >= 0) {
+      double* Srow = Sx + (size_t)(1 + srow) * NP + 1;
+      // the last term of each column group carries the column and closes it
+      double acc = 0.0;
+      // software-pipelined: the next pass's term words are in flight while
+      // this pass is summed; the pass itself has no branch except the column
+      // store
+      uint64_t nx[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) nx[u] = tb + u < te ? tl.term[tb + u] : 0ull;
+      for (int u = 0; u < 8; ++u) nx[u] = tb + u < te ? tl.term[tb + u] : 0ull;
 #pragma clang loop unroll(disable)
-    for (int ti = tb; ti < te; ti += 8) {
-      uint64_t tw8[8];
+      for (int ti = tb; ti < te; ti += 8) {
+        uint64_t tw8[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        tw8[u] = nx[u];
-        nx[u] = ti + 8 + u < te ? tl.term[ti + 8 + u] : 0ull;
-      }
-      // the efficiencies of third-body terms (from the LDS copy)
-      double ef8[8];
+        for (int u = 0; u < 8; ++u) {
+          tw8[u] = nx[u];
+          nx[u] = ti + 8 + u < te ? tl.term[ti + 8 + u] : 0ull;
+        }
+        // the efficiencies of third-body terms (from the LDS copy)
+        double ef8[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        ef8[u] = (ti + u < te && ((tw8[u] >> 16) & 7) == 6) ? w.tbd[(tw8[u] >> 48) & 0xFFF] : 0.0;
+        for (int u = 0; u < 8; ++u)
+          ef8[u] = (ti + u < te && ((tw8[u] >> 16) & 7) == 6) ? w.tbd[(tw8[u] >> 48) & 0xFFF] : 0.0;
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const bool in = ti + u < te;  // past the row's end the word is 0: indices 0, no store
-        const uint64_t tw = tw8[u];
-        const int r = (int)(tw & 0xFFFF);
-        const int kind = (int)((tw >> 16) & 7);
-        const double nu = (double)(int8_t)((tw >> 24) & 0xFF);
-        const double co = w.C[(tw >> 32) & 0xFF] * w.C[(tw >> 40) & 0xFF];
-        // one rate load per term: the array is picked by the kind
-        const double rv = (kind < 3 ? w.rk : (kind < 6 ? w.rkr : w.rdm))[r];
-        const double v = (kind >= 3 && kind < 6 ? -rv : rv) * (kind < 6 ? co : ef8[u]);
-        const double an = acc + nu * v;
-        acc = in ? an : acc;
-        if (in && ((tw >> 19) & 1)) {
-          const int col = (int)(((tw >> 20) & 0xF) | (((tw >> 60) & 0xF) << 4));
-          Srow[col] = acc;
-          sk += w.C[col] * acc;
-          acc = 0.0;
+        for (int u = 0; u < 8; ++u) {
+          const bool in = ti + u < te;  // past the segment's end the word is 0: indices 0, no store
+          const uint64_t tw = tw8[u];
+          const int r = (int)(tw & 0xFFFF);
+          const int kind = (int)((tw >> 16) & 7);
+          const double nu = (double)(int8_t)((tw >> 24) & 0xFF);
+          const double co = w.C[(tw >> 32) & 0xFF] * w.C[(tw >> 40) & 0xFF];
+          // one rate load per term: the array is picked by the kind
+          const double rv = (kind < 3 ? w.rk : (kind < 6 ? w.rkr : w.rdm))[r];
+          const double v = (kind >= 3 && kind < 6 ? -rv : rv) * (kind < 6 ? co : ef8[u]);
+          const double an = acc + nu * v;
+          acc = in ? an : acc;
+          if (in && ((tw >> 19) & 1)) {
+            const int col = (int)(((tw >> 20) & 0xF) | (((tw >> 60) & 0xF) << 4));
+            Srow[col] = acc;
+            skt += w.C[col] * acc;
+            acc = 0.0;
+          }
         }
       }
     }
+    w.skp[t] = skt;
+    __syncthreads();
+    // a split row's two partial sums, first segment first
+    if (isSp) sk = sg[3] >= 0 ? w.skp[t] + w.skp[sg[3]] : w.skp[t];
   }
   // sk = sum_l C_l (S_kl + adense_k); C sums to Ctot
   if (isSp) {
