@@ -13,7 +13,8 @@
 // MFMA (16 x 16 output tiles, operands from LDS).  The Jacobian
 // is assembled without atomics: every species row walks a host-built list of
 // its nonzero columns, each with the reaction terms that contribute to it, in
-// a fixed order.  All sums over threads are fixed-order, so results are
+// a fixed order (the longest rows in two segments, the second one on a thread
+// that owns no row).  All sums over threads are fixed-order, so results are
 // bitwise reproducible.
 #pragma once
 #include "chem_cell.hpp"
